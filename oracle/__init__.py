@@ -1,0 +1,13 @@
+"""CPU FP64 oracle — TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, step-by-step NumPy/SciPy implementations of what the GPU path
+computes, used by the tests, by the package's smoke check and by the
+benchmark's CPU-baseline leg.  The product path never imports this package,
+and this package imports nothing from the product path: the two share only
+the seeded input generator in ``synth``.
+"""
+from .scocg import (  # noqa: F401
+    CONVERGED, MAXITER, BREAKDOWN, NONFINITE, ScocgResult, initial_seed,
+    inner_cg, scocg, local_system, solve_rhs, solve_problem,
+)
+from .dense import dense_solve, green_eig, true_residual  # noqa: F401

@@ -1,0 +1,321 @@
+"""Pins for the CPU oracle: each test ties it to something other than itself.
+
+* plain definition: dense LU of (z S - H) (Sec. 3, Eq. 2);
+* eigen-expansion of G through H y = lambda S y (Sec. 2, Eq. 1);
+* COCG with a real shift above the spectrum and S = I is textbook CG;
+* closed forms: diagonal H, a 2x2 H, a block-diagonal H;
+* collinearity of the shifted residuals with the seed's;
+* symmetry G_ij = G_ji, G(conj z) = conj G(z), Herglotz sign;
+* the sum rule and the DOS as a broadened eigenvalue histogram (Sec. 8);
+* seed switching does not change the answer beyond the a-priori bound;
+* the inner CG against a Cholesky solve;
+* breakdown / status handling.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from oracle import (BREAKDOWN, CONVERGED, MAXITER, NONFINITE, dense_solve, green_eig,
+                    initial_seed, inner_cg, scocg, solve_rhs, true_residual)
+from synth import bsr_to_dense, bsr_to_scipy, make_config, make_problem
+
+
+def _unit(M, j):
+    b = np.zeros(M, dtype=np.complex128)
+    b[j] = 1.0
+    return b
+
+
+_EIG_CACHE = {}
+
+
+def _inv_norm_bound(H, S, z):
+    """||(z S - H)^{-1}||_2 (exact, dense; S = I: 1 / min_k |z - lambda_k|)."""
+    Hd = H.toarray() if hasattr(H, "toarray") else H
+    if S is None:
+        key = id(H)
+        if key not in _EIG_CACHE:
+            _EIG_CACHE[key] = (H, np.linalg.eigvalsh(Hd))
+        return 1.0 / np.abs(z - _EIG_CACHE[key][1]).min()
+    Sd = np.eye(Hd.shape[0]) if S is None else (S.toarray() if hasattr(S, "toarray") else S)
+    return 1.0 / np.linalg.svd(z * Sd - Hd, compute_uv=False)[-1]
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    p = make_config(0)
+    return p, bsr_to_scipy(p.H)
+
+
+@pytest.fixture(scope="module")
+def gen_small():
+    p = make_problem(lattice="sc", L=3, bdim=4, s_scale=0.03, K=12, eta=0.05, nrhs=3,
+                     seed_key=(7, 7, 7))
+    return p, bsr_to_scipy(p.H), bsr_to_scipy(p.S)
+
+
+def test_cfg0_vs_dense_lu(cfg0):
+    p, H = cfg0
+    for j in range(p.nrhs):
+        G, res, orb = solve_rhs(p, j, full_x=True)
+        assert np.all(res.status == CONVERGED)
+        b = _unit(p.M, p.rhs[j])
+        for k, z in enumerate(p.shifts):
+            xs = dense_solve(H, None, z, b)
+            tr = true_residual(H, None, z, b, res.x[:, k])
+            assert tr < 2 * p.tol                       # recursive estimate tracks the truth
+            err = np.linalg.norm(res.x[:, k] - xs)
+            assert err <= _inv_norm_bound(H, None, z) * 2 * p.tol
+        # the G output rows are the x entries
+        assert np.array_equal(G, res.x[np.searchsorted(orb, p.outs(j)), :].T)
+
+
+def test_generalized_vs_dense_lu_and_eig(gen_small):
+    p, H, S = gen_small
+    for j in range(p.nrhs):
+        G, res, orb = solve_rhs(p, j, full_x=True)
+        assert np.all(res.status == CONVERGED)
+        b = _unit(p.M, p.rhs[j])
+        for k, z in enumerate(p.shifts):
+            xs = dense_solve(H, S, z, b)
+            assert true_residual(H, S, z, b, res.x[:, k]) < 2 * p.tol
+            assert np.linalg.norm(res.x[:, k] - xs) <= _inv_norm_bound(H, S, z) * 2 * p.tol
+        gjj = green_eig(H, S, p.shifts, p.rhs[j], p.rhs[j])
+        assert np.allclose(res.x[p.rhs[j], :], gjj, rtol=0, atol=1e-8 * np.abs(gjj).max())
+
+
+def test_eigen_expansion_cfg0(cfg0):
+    p, H = cfg0
+    G, res, orb = solve_rhs(p, 0, full_x=True)
+    j = int(p.rhs[0])
+    for i in (j, (j + 1) % p.M, int(p.outs(0)[-1])):
+        gij = green_eig(H, None, p.shifts, i, j)
+        assert np.abs(res.x[i, :] - gij).max() <= 20 * 2 * p.tol   # ||A^-1|| <= 1/eta = 20
+
+
+def _textbook_cg(A, b, n):
+    x = np.zeros_like(b)
+    r = b.copy()
+    d = r.copy()
+    for _ in range(n):
+        Ad = A @ d
+        a = (r @ r) / (d @ Ad)
+        x = x + a * d
+        rn = r - a * Ad
+        d = rn + (rn @ rn) / (r @ r) * d
+        r = rn
+    return x
+
+
+def test_cocg_equals_cg_for_real_shift(cfg0):
+    p, H = cfg0
+    Hd = H.toarray()
+    lmax = np.linalg.eigvalsh(Hd)[-1]
+    z = lmax + 3.0
+    b = _unit(p.M, 17)
+    A = z * np.eye(p.M) - Hd
+    for n in (1, 2, 5, 10, 20):
+        res = scocg(H, None, np.array([z + 0j]), b, tol=1e-300, maxiter=n)
+        xr = _textbook_cg(A, b.real, n)
+        assert np.abs(res.x[:, 0].imag).max() == 0.0
+        assert np.allclose(res.x[:, 0].real, xr, rtol=0, atol=1e-12 * np.abs(xr).max())
+
+
+def test_diagonal_H_one_iteration():
+    h = np.array([0.3, -1.2, 2.5, 0.7])
+    H = sp.diags(h).tocsr()
+    z = np.array([-1.0 + 0.1j, 0.5 + 0.1j, 2.0 + 0.2j])
+    trace = []
+    res = scocg(H, None, z, _unit(4, 2), tol=1e-12, record=lambda n, st: trace.append(st))
+    assert res.n_outer == 1 and np.all(res.iters == 1)
+    assert np.allclose(res.x[2, :], 1.0 / (z - h[2]), rtol=1e-15, atol=0)
+    assert np.all(res.x[[0, 1, 3], :] == 0)
+    s = initial_seed(z)
+    assert np.allclose(trace[0]["pi"], (z - h[2]) / (z[s] - h[2]), rtol=1e-14)
+
+
+def test_2x2_closed_form():
+    h11, h22, h12 = 0.4, -0.9, 0.35
+    H = sp.csr_matrix(np.array([[h11, h12], [h12, h22]]))
+    z = np.array([-2.0 + 0.05j, 0.1 + 0.05j, 1.3 + 0.3j, -0.5 - 0.2j])
+    res = scocg(H, None, z, _unit(2, 0), tol=1e-13)
+    assert res.n_outer <= 2 and np.all(res.status == CONVERGED)
+    g11 = (z - h22) / ((z - h11) * (z - h22) - h12 ** 2)
+    g21 = h12 / ((z - h11) * (z - h22) - h12 ** 2)
+    assert np.allclose(res.x[0], g11, rtol=1e-12)
+    assert np.allclose(res.x[1], g21, rtol=1e-12)
+
+
+def test_block_diagonal_H_converges_in_block_dim():
+    p = make_problem(lattice="sc", L=4, bdim=4, hop=(0.0, 0.0), K=8, eta=0.05, nrhs=3)
+    H = bsr_to_scipy(p.H)
+    for j in range(p.nrhs):
+        G, res, orb = solve_rhs(p, j, full_x=True)
+        assert res.n_outer <= 4 and np.all(res.status == CONVERGED)
+        a = int(p.rhs[j]) // 4
+        Haa = H[a * 4:(a + 1) * 4, a * 4:(a + 1) * 4].toarray()
+        for k, z in enumerate(p.shifts):
+            Gaa = np.linalg.inv(z * np.eye(4) - Haa)
+            assert np.allclose(res.x[a * 4:(a + 1) * 4, k], Gaa[:, int(p.rhs[j]) % 4], atol=1e-12)
+
+
+@pytest.mark.parametrize("generalized", [False, True])
+def test_collinear_residuals(cfg0, gen_small, generalized):
+    if generalized:
+        p, H, S = gen_small
+    else:
+        (p, H), S = cfg0, None
+    j = int(p.rhs[0])
+    b = _unit(p.M, j)
+    err = []
+
+    def rec(n, st):
+        if n >= 30:
+            return
+        for k, z in enumerate(p.shifts):
+            xk = st["x"][:, k]
+            Ax = z * (xk if S is None else S @ xk) - H @ xk
+            err.append(np.linalg.norm((b - Ax) - st["rho"] / st["pi"][k]))
+    kw = {}
+    if S is not None:       # exact S^-1, so that only the recurrences are tested
+        c = sla.cho_factor(S.toarray())
+        kw["s_solve"] = lambda v: sla.cho_solve(c, v)
+    scocg(H, S, p.shifts, b, tol=p.tol, maxiter=30, record=rec, **kw)
+    assert max(err) <= 1e-12
+
+
+def test_symmetry_conjugation_herglotz(cfg0):
+    p, H = cfg0
+    i, j = int(p.rhs[0]), int(p.rhs[1])
+    Gi, ri, _ = solve_rhs(p, 0, full_x=True)
+    Gj, rj, _ = solve_rhs(p, 1, full_x=True)
+    assert np.abs(ri.x[j, :] - rj.x[i, :]).max() <= 2 * 20 * 2 * p.tol     # G_ji = G_ij
+    # conjugate shifts
+    res_c = scocg(H, None, np.conj(p.shifts), _unit(p.M, i), tol=p.tol)
+    assert np.abs(res_c.x - np.conj(ri.x)).max() <= 2 * 20 * 2 * p.tol
+    assert np.all(-ri.x[i, :].imag > 0)                                    # Herglotz, eta > 0
+
+
+def test_sum_rule_and_dos():
+    """-(1/pi) int Im G_jj dE: closed form over a window, ~1 over the real line;
+    the trace over all unit RHS is the Lorentzian-broadened eigenvalue histogram."""
+    eta = 0.5
+    p = make_problem(lattice="sc", L=3, bdim=4, K=2, eta=eta, nrhs=4, seed_key=(9, 9, 9))
+    H = bsr_to_scipy(p.H)
+    lam, Y = np.linalg.eigh(H.toarray())
+    a, bnd = lam[0] - 20.0, lam[-1] + 20.0
+    h = eta / 3.0
+    E = np.linspace(a, bnd, int(np.ceil((bnd - a) / h)) + 1)
+    z = E + 1j * eta
+    j = int(p.rhs[0])
+    res = scocg(H, None, z, _unit(p.M, j), tol=1e-12)
+    assert np.all(res.status == CONVERGED)
+    f = -res.x[j, :].imag / np.pi
+    integral = np.sum((f[1:] + f[:-1]) * np.diff(E)) / 2
+    w = Y[j, :] ** 2
+    closed = np.sum(w * (np.arctan((bnd - lam) / eta) - np.arctan((a - lam) / eta)) / np.pi)
+    assert abs(integral - closed) < 1e-6
+    assert abs(integral - 1.0) < (2 * eta / np.pi) / 20
+    # DOS: sum over all M unit RHS at a few energies
+    Ez = np.array([-3.0, -0.4, 0.0, 1.7, 5.0]) + 1j * eta
+    tr = np.zeros(Ez.size)
+    for jj in range(p.M):
+        r = scocg(H, None, Ez, _unit(p.M, jj), tol=1e-12)
+        tr += -r.x[jj, :].imag / np.pi
+    hist = np.sum((eta / np.pi) / ((Ez.real[:, None] - lam[None, :]) ** 2 + eta ** 2), axis=1)
+    assert np.allclose(tr, hist, rtol=1e-8)
+
+
+def test_generalized_sum_rule(gen_small):
+    """With S: the full-line integral of -(1/pi) Im G_jj is (S^-1)_jj; the window
+    integral matches the closed form from H y = lambda S y."""
+    p, H, S = gen_small
+    eta = 0.5
+    lam, Y = sla.eigh(H.toarray(), S.toarray())
+    a, bnd = lam[0] - 20.0, lam[-1] + 20.0
+    E = np.linspace(a, bnd, int(np.ceil((bnd - a) / (eta / 3))) + 1)
+    j = int(p.rhs[0])
+    res = scocg(H, S, E + 1j * eta, _unit(p.M, j), tol=1e-12)
+    f = -res.x[j, :].imag / np.pi
+    integral = np.sum((f[1:] + f[:-1]) * np.diff(E)) / 2
+    w = Y[j, :] ** 2
+    closed = np.sum(w * (np.arctan((bnd - lam) / eta) - np.arctan((a - lam) / eta)) / np.pi)
+    assert abs(integral - closed) < 1e-6
+    sinv_jj = np.linalg.inv(S.toarray())[j, j]
+    assert abs(np.sum(w) - sinv_jj) < 1e-12
+    assert abs(integral - sinv_jj) < (2 * eta / np.pi) / 20 * sinv_jj
+
+
+def test_seed_switching_invariance(cfg0):
+    p, H = cfg0
+    j = int(p.rhs[2])
+    b = _unit(p.M, j)
+    fastest = int(np.argmax(np.abs(p.shifts.real)))
+    auto = scocg(H, None, p.shifts, b, tol=p.tol)
+    forced = scocg(H, None, p.shifts, b, tol=p.tol, seed=fastest)
+    assert len(forced.seeds) > 1 and forced.seeds[0] == (0, fastest)
+    assert np.all(forced.status == CONVERGED)
+    for k, z in enumerate(p.shifts):
+        bound = _inv_norm_bound(H, None, z) * 2 * p.tol
+        xs = dense_solve(H, None, z, b)
+        assert np.linalg.norm(forced.x[:, k] - xs) <= bound
+        assert np.linalg.norm(forced.x[:, k] - auto.x[:, k]) <= 2 * bound
+
+
+def test_seed_switching_generalized(gen_small):
+    p, H, S = gen_small
+    j = int(p.rhs[1])
+    b = _unit(p.M, j)
+    forced = scocg(H, S, p.shifts, b, tol=p.tol, seed=0)
+    assert len(forced.seeds) > 1
+    for k, z in enumerate(p.shifts):
+        xs = dense_solve(H, S, z, b)
+        assert np.linalg.norm(forced.x[:, k] - xs) <= _inv_norm_bound(H, S, z) * 2 * p.tol
+
+
+def test_inner_cg_vs_cholesky(gen_small):
+    p, H, S = gen_small
+    rng = np.random.default_rng(5)
+    rho = rng.normal(size=p.M) + 1j * rng.normal(size=p.M)
+    r, it = inner_cg(S, rho, 1e-13, 1000)
+    c = sla.cho_factor(S.toarray())
+    ref = sla.cho_solve(c, rho)
+    assert np.linalg.norm(r - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert 3 < it < 60
+    # whole solve with an exact S^-1 agrees within the a-priori bound
+    b = _unit(p.M, int(p.rhs[0]))
+    a1 = scocg(H, S, p.shifts, b, tol=p.tol)
+    a2 = scocg(H, S, p.shifts, b, tol=p.tol, s_solve=lambda v: sla.cho_solve(c, v))
+    for k, z in enumerate(p.shifts):
+        assert np.linalg.norm(a1.x[:, k] - a2.x[:, k]) <= 2 * _inv_norm_bound(H, S, z) * 2 * p.tol
+
+
+def test_initial_seed_rule():
+    z = np.array([-1 + 0.1j, 0.0 + 0.05j, 3 + 0.05j, 0.2 + 0.05j])
+    assert initial_seed(z) == 1                      # smallest |Im|, then nearest median
+    z = np.array([-1 + 0.1j, 1 + 0.1j, -0.5 + 0.1j, 0.5 + 0.1j])
+    assert initial_seed(z) == 2                      # median 0: tie between 2 and 3 -> lowest k
+    assert initial_seed(make_config(0).shifts) == 15
+    assert initial_seed(np.array([2 + 0.1j])) == 0
+
+
+def test_status_paths(cfg0):
+    p, H = cfg0
+    b = _unit(p.M, int(p.rhs[0]))
+    # maxiter = 1: MAXITER with partial results
+    r1 = scocg(H, None, p.shifts, b, tol=p.tol, maxiter=1)
+    assert np.all(r1.status == MAXITER) and r1.n_outer == 1
+    assert np.all(r1.x[int(p.rhs[0]), :] != 0)
+    # non-finite input
+    Hn = H.copy().tolil()
+    Hn[3, 3] = np.nan
+    rn = scocg(Hn.tocsr(), None, p.shifts, _unit(p.M, 3), tol=p.tol)
+    assert np.all(rn.status == NONFINITE)
+    # zero RHS: x = 0, converged at 0 iterations
+    r0 = scocg(H, None, p.shifts, np.zeros(p.M), tol=p.tol)
+    assert np.all(r0.status == CONVERGED) and np.all(r0.x == 0)
+    # real shift on an eigenvalue of a diagonal matrix: never a silent wrong answer
+    Hd = sp.diags([1.0, 2.0, 3.0]).tocsr()
+    rb = scocg(Hd, None, np.array([2.0 + 0j, 2.5 + 0.1j]), np.ones(3), tol=1e-12, seed=0, maxiter=50)
+    assert rb.status[0] in (BREAKDOWN, NONFINITE, MAXITER)
