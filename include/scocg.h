@@ -1,0 +1,232 @@
+/*
+ * scocg — generalized shifted COCG Green's-function solver for MI355X (gfx950).
+ *
+ * The library solves the generalized shifted linear equations
+ *
+ *         (z_k S - H) x_j(z_k) = e_j,      k = 0..K-1,  j in a set of RHS,
+ *
+ * (Sec. 3, Eq. 2 of Hoshi et al., "Novel linear algebraic theory and
+ * one-hundred-million-atom quantum material simulations on the K computer")
+ * for a real symmetric H and a real symmetric positive definite S (Sec. 2;
+ * S = NULL means S = I, the standard shifted problem of Sec. 3), and returns
+ * the Green's-function elements G_ij(z_k) = e_i^T x_j(z_k) for requested
+ * rows i (the Green's function as the analysis object, Sec. 2-3), or the
+ * whole x_j(z_k).  The method is the generalized shifted conjugate
+ * orthogonal CG (Sec. 3, item (i)): one Krylov subspace per RHS, built for a
+ * seed shift; every other shift follows by scalar recurrences; the seed is
+ * switched when it converges first.  In the order-N form each RHS may be
+ * restricted to a local cluster of atoms (principal submatrices of H and S),
+ * following the paper's order-N principle (Sec. 2).
+ *
+ * Conventions for every call:
+ *   - Plain C types and pointers only.  "host" pointers are ordinary CPU
+ *     memory; "device" pointers are HIP device memory on the current device.
+ *   - Nothing here aborts or throws.  Negative return codes are hard errors,
+ *     SCOCG_OK (0) is success, positive codes are warnings.  The message of
+ *     the last failure on the calling thread is scocg_last_error().
+ *   - Objects are owned by the library and released by their _free call,
+ *     which accepts NULL.
+ *   - A plan is bound to one device and is not safe to run from two threads
+ *     or streams at once.
+ */
+#ifndef SCOCG_H
+#define SCOCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes --------------------------------------------------------- */
+typedef int32_t scocg_status;
+#define SCOCG_OK                 0
+#define SCOCG_W_PARTIAL          1   /* some (RHS, shift) pair did not converge */
+#define SCOCG_W_S_DIAG           2   /* S has a diagonal element != 1 (accepted) */
+#define SCOCG_E_ARG            (-1)  /* NULL / negative / out-of-range argument */
+#define SCOCG_E_SHAPE          (-2)  /* malformed sparse structure */
+#define SCOCG_E_NOT_SYMMETRIC  (-3)  /* block (a,b) != block (b,a)^T exactly */
+#define SCOCG_E_DEVICE         (-4)  /* HIP runtime error (message says which) */
+#define SCOCG_E_NOMEM          (-5)  /* device or host allocation failed */
+#define SCOCG_E_UNSUPPORTED    (-6)  /* block size / shift count not compiled in */
+
+/* ---- per-(RHS, shift) result codes ---------------------------------------- */
+#define SCOCG_CONVERGED  0   /* recursive residual estimate < tol * ||b|| */
+#define SCOCG_MAXITER    1   /* iteration limit reached; partial x returned */
+#define SCOCG_BREAKDOWN  2   /* zero pivot (mu = 0, pi = 0 or gamma = 0) */
+#define SCOCG_NONFINITE  3   /* NaN / Inf met in the recurrences */
+
+/* ---- precision of the vectors and stored blocks --------------------------- */
+#define SCOCG_FP64        0  /* complex128 vectors, FP64 blocks */
+#define SCOCG_FP32        1  /* complex64 vectors and SpMV, FP32 blocks; FP64
+                                scalars, FP64 residual replacement, FP64 audit */
+#define SCOCG_FP32_BF16   2  /* as SCOCG_FP32 but blocks stored as bfloat16 */
+
+/* ---- output modes --------------------------------------------------------- */
+#define SCOCG_OUT_SELECTED_G  0  /* G_ij for the rows i listed per RHS */
+#define SCOCG_OUT_FULL_X      1  /* the whole x_j(z_k) (cluster-local order) */
+
+typedef struct { double re, im; } scocg_z;
+
+typedef struct scocg_matrix  scocg_matrix;
+typedef struct scocg_problem scocg_problem;
+typedef struct scocg_plan    scocg_plan;
+
+/* Thread-local message describing the last failing call ("" if none). */
+const char* scocg_last_error(void);
+
+/* Library version string. */
+const char* scocg_version(void);
+
+/* ---- matrices ------------------------------------------------------------- */
+/*
+ * A square block-sparse-row matrix over nbrows block rows of bdim x bdim
+ * blocks (the LCAO orbital blocks of one atom pair, Sec. 8).
+ *   rowptr  host int64[nbrows+1], rowptr[0] = 0, non-decreasing
+ *   colidx  host int32[rowptr[nbrows]], strictly ascending within a row,
+ *           each in [0, nbrows)
+ *   vals    host double[rowptr[nbrows] * bdim * bdim], row-major per block:
+ *           vals[(e*bdim + r)*bdim + c] = A(a*bdim + r, colidx[e]*bdim + c)
+ * The arrays are copied; the caller keeps ownership of its buffers.  The
+ * matrix must be exactly symmetric: for every block (a,b) the block (b,a)
+ * must be present and equal to its transpose (SCOCG_E_NOT_SYMMETRIC).
+ * bdim must be 1..16 (the solver runs bdim 4 and 9; others give
+ * SCOCG_E_UNSUPPORTED at plan creation).
+ */
+scocg_status scocg_matrix_from_bsr(int64_t nbrows, int32_t bdim, const int64_t* rowptr,
+                                   const int32_t* colidx, const double* vals,
+                                   scocg_matrix** out);
+
+/*
+ * Same from scalar CSR (n x n, host arrays, columns ascending per row),
+ * regrouped into bdim x bdim blocks; n must be a multiple of bdim.
+ */
+scocg_status scocg_matrix_from_csr(int64_t n, const int64_t* rowptr, const int32_t* colidx,
+                                   const double* vals, int32_t bdim, scocg_matrix** out);
+
+void scocg_matrix_free(scocg_matrix* m);
+
+/* ---- problem: H and S resident on the device ------------------------------ */
+/*
+ * Merges the block patterns of H and S and uploads the values to device
+ * memory owned by the problem (FP64, plus FP32/BF16 copies on first use by
+ * a plan that asks for them).  S may be NULL (S = I).  H and S must have the
+ * same nbrows and bdim.  S's diagonal is checked: a diagonal element != 1 is
+ * accepted with SCOCG_W_S_DIAG (the method only needs S SPD; a non-SPD S is
+ * detected by the inner CG and reported as BREAKDOWN).
+ */
+scocg_status scocg_problem_create(const scocg_matrix* H, const scocg_matrix* S,
+                                  scocg_problem** out);
+void scocg_problem_free(scocg_problem* p);
+
+/* ---- options -------------------------------------------------------------- */
+typedef struct {
+    double  tol;            /* converge when ||rho|| / |pi_k| < tol * ||b|| (> 0) */
+    int32_t maxiter;        /* outer iterations; 0 = max(1000, 4*M_j) */
+    int32_t precision;      /* SCOCG_FP64 / SCOCG_FP32 / SCOCG_FP32_BF16 */
+    int32_t replace_every;  /* FP32 forms: FP64 residual replacement period; 0 = off */
+    int32_t inner_maxiter;  /* inner CG iteration cap */
+    double  inner_tol;      /* inner CG stop: ||res|| <= inner_tol * ||rho|| (FP64) */
+    double  inner_tol_lo;   /* same for the FP32 inner CG */
+    int32_t seed_index;     /* initial seed; -1 = rule: smallest |Im z|, then Re z
+                               nearest the median of Re z, then lowest index */
+    int32_t threads;        /* workgroup size 256/512/1024; 0 = default */
+    int32_t slots;          /* resident workgroups; 0 = device CUs x occupancy */
+    int32_t audit;          /* FP32 forms: FP64 true-residual audit + FP64 fallback */
+} scocg_options;
+
+/* Defaults: tol 1e-10, maxiter 0, FP64, replace_every 20, inner_maxiter 1000,
+ * inner_tol 1e-13, inner_tol_lo 1e-6, seed_index -1, threads 0, slots 0, audit 1. */
+void scocg_options_default(scocg_options* opt);
+
+/* ---- right-hand sides ----------------------------------------------------- */
+/*
+ * RHS number r (0..nrhs-1) is the unit vector e_j with j = rhs_index[r] (a
+ * global orbital index).
+ *   cluster_ptr/cluster_atoms  host CSR over RHS of global atom indices,
+ *           strictly ascending per RHS; NULL = every RHS uses the whole
+ *           system.  The atom of orbital j must be in RHS r's cluster.  The
+ *           cluster system is the principal submatrix of (z S - H) on the
+ *           cluster's orbitals, in ascending global order.
+ *   out_mode SCOCG_OUT_SELECTED_G: out_ptr/out_rows (host CSR over RHS of
+ *           global orbital indices, each inside the RHS's cluster) name the
+ *           rows i of G_ij to return.  SCOCG_OUT_FULL_X: out_ptr/out_rows are
+ *           ignored and the whole cluster-local x is returned.
+ *   order   optional host permutation of 0..nrhs-1: the order in which RHS
+ *           are handed to the GPU's work queue (a scheduler's choice; it
+ *           changes timing only).  NULL = index order.
+ * All arrays are read during the call only.
+ */
+typedef struct {
+    const int64_t* cluster_ptr;
+    const int32_t* cluster_atoms;
+    int32_t        out_mode;
+    const int64_t* out_ptr;
+    const int32_t* out_rows;
+    const int32_t* order;
+} scocg_rhs_spec;
+
+/* ---- plans ---------------------------------------------------------------- */
+/*
+ * Validates the shifts and RHS, builds the per-RHS local block maps (order-N
+ * clusters) on the host and uploads everything the solve reads, plus the
+ * per-workgroup working memory, to the device.  After this call a run reads
+ * only device memory.
+ *   nshift  K >= 1 (at most 512), shifts host scocg_z[K]
+ *   nrhs    >= 0, rhs_index host int32[nrhs]
+ */
+scocg_status scocg_plan_create(scocg_problem* P, const scocg_options* opt, int32_t nshift,
+                               const scocg_z* shifts, int32_t nrhs, const int32_t* rhs_index,
+                               const scocg_rhs_spec* spec, scocg_plan** out);
+void scocg_plan_free(scocg_plan* plan);
+
+/*
+ * Number of complex output values of a run: sum over RHS of K * n_out(r),
+ * where n_out(r) is the length of RHS r's out_rows list (SELECTED_G) or its
+ * cluster dimension (FULL_X).  The values of RHS r start at
+ * K * out_offset(r) and are laid out [shift][row].
+ */
+int64_t scocg_plan_out_count(const scocg_plan* plan);
+/* out_offset(r) for every RHS (host int64[nrhs+1], prefix sums of n_out). */
+scocg_status scocg_plan_out_offsets(const scocg_plan* plan, int64_t* offsets);
+
+/*
+ * Runs the whole solve on `stream` (a hipStream_t; NULL = default stream),
+ * asynchronously.  All outputs are caller-owned DEVICE buffers:
+ *   out    scocg_z[scocg_plan_out_count]     G_ij(z_k) or x
+ *   iters  int32[nrhs*K]  iteration at which (r,k) converged (-1 if not)
+ *   status int8[nrhs*K]   SCOCG_CONVERGED / MAXITER / BREAKDOWN / NONFINITE
+ *   resid  double[nrhs*K] final residual estimate ||rho||/|pi_k| / ||b||;
+ *                         for the FP32 forms with audit on, the audited FP64
+ *                         true residual ||b - (z_k S - H) x|| / ||b||
+ * Any output pointer may be NULL except out.  Returns after enqueueing.
+ */
+scocg_status scocg_plan_run(scocg_plan* plan, void* stream, scocg_z* out, int32_t* iters,
+                            int8_t* status, double* resid);
+
+/*
+ * Per-RHS counters of the last run, copied to host int64[nrhs * SCOCG_NSTAT]
+ * (synchronises the run's stream):
+ *   [0] outer iterations   [1] sum over iterations of shifts updated
+ *   [2] inner CG iterations [3] seed switches  [4] cluster dimension M_r
+ *   [5] block entries of the local pattern     [6] residual replacements
+ *   [7] fallback (FP64 re-solve) outer iterations
+ */
+#define SCOCG_NSTAT 8
+scocg_status scocg_plan_stats(scocg_plan* plan, int64_t* stats);
+
+/*
+ * Convenience: plan_create + plan_run + copy back + plan_free, all on host
+ * buffers (out sized as scocg_plan_out_count would report; iters, status,
+ * resid sized nrhs*K; any of those three may be NULL).  Synchronous.
+ * Returns SCOCG_W_PARTIAL if any pair did not converge.
+ */
+scocg_status scocg_solve(scocg_problem* P, const scocg_options* opt, int32_t nshift,
+                         const scocg_z* shifts, int32_t nrhs, const int32_t* rhs_index,
+                         const scocg_rhs_spec* spec, scocg_z* out, int32_t* iters,
+                         int8_t* status, double* resid);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCOCG_H */

@@ -1,0 +1,317 @@
+"""ctypes binding of libscocg.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts NumPy
+arrays to pointers, wraps the opaque handles, and uses torch for device
+buffers and streams.  Loading fails loudly if the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libscocg.so")
+
+# return codes (include/scocg.h)
+OK, W_PARTIAL, W_S_DIAG = 0, 1, 2
+E_ARG, E_SHAPE, E_NOT_SYMMETRIC, E_DEVICE, E_NOMEM, E_UNSUPPORTED = -1, -2, -3, -4, -5, -6
+CONVERGED, MAXITER, BREAKDOWN, NONFINITE = 0, 1, 2, 3
+FP64, FP32, FP32_BF16 = 0, 1, 2
+OUT_SELECTED_G, OUT_FULL_X = 0, 1
+NSTAT = 8
+STAT_NAMES = ("outer", "sum_upd", "inner", "switches", "M", "blocks", "replacements", "fallback")
+
+EXPORTS = (
+    "scocg_last_error", "scocg_version", "scocg_matrix_from_bsr", "scocg_matrix_from_csr",
+    "scocg_matrix_free", "scocg_problem_create", "scocg_problem_free", "scocg_options_default",
+    "scocg_plan_create", "scocg_plan_free", "scocg_plan_out_count", "scocg_plan_out_offsets",
+    "scocg_plan_run", "scocg_plan_stats", "scocg_solve",
+)
+
+
+class ScocgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"scocg error {code}: {msg}")
+        self.code = code
+
+
+class scocg_z(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class scocg_options(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxiter", C.c_int32), ("precision", C.c_int32),
+                ("replace_every", C.c_int32), ("inner_maxiter", C.c_int32), ("inner_tol", C.c_double),
+                ("inner_tol_lo", C.c_double), ("seed_index", C.c_int32), ("threads", C.c_int32),
+                ("slots", C.c_int32), ("audit", C.c_int32)]
+
+
+class scocg_rhs_spec(C.Structure):
+    _fields_ = [("cluster_ptr", C.c_void_p), ("cluster_atoms", C.c_void_p), ("out_mode", C.c_int32),
+                ("out_ptr", C.c_void_p), ("out_rows", C.c_void_p), ("order", C.c_void_p)]
+
+
+_VP = C.c_void_p
+_LIB = None
+
+
+def _declare(lib):
+    i32, i64, st = C.c_int32, C.c_int64, C.c_int32
+    sig = {
+        "scocg_last_error": (C.c_char_p, []),
+        "scocg_version": (C.c_char_p, []),
+        "scocg_matrix_from_bsr": (st, [i64, i32, _VP, _VP, _VP, C.POINTER(_VP)]),
+        "scocg_matrix_from_csr": (st, [i64, _VP, _VP, _VP, i32, C.POINTER(_VP)]),
+        "scocg_matrix_free": (None, [_VP]),
+        "scocg_problem_create": (st, [_VP, _VP, C.POINTER(_VP)]),
+        "scocg_problem_free": (None, [_VP]),
+        "scocg_options_default": (None, [C.POINTER(scocg_options)]),
+        "scocg_plan_create": (st, [_VP, C.POINTER(scocg_options), i32, _VP, i32, _VP,
+                                   C.POINTER(scocg_rhs_spec), C.POINTER(_VP)]),
+        "scocg_plan_free": (None, [_VP]),
+        "scocg_plan_out_count": (i64, [_VP]),
+        "scocg_plan_out_offsets": (st, [_VP, _VP]),
+        "scocg_plan_run": (st, [_VP, _VP, _VP, _VP, _VP, _VP]),
+        "scocg_plan_stats": (st, [_VP, _VP]),
+        "scocg_solve": (st, [_VP, C.POINTER(scocg_options), i32, _VP, i32, _VP,
+                             C.POINTER(scocg_rhs_spec), _VP, _VP, _VP, _VP]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+def load(path: str = LIB_PATH):
+    """Load libscocg.so; raises if it is missing (no fallback exists)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is not built: run `python -m paper_1402_7285_amd.build`")
+        _LIB = _declare(C.CDLL(path))
+    return _LIB
+
+
+def _check(code):
+    if code < 0:
+        raise ScocgError(code, load().scocg_last_error().decode())
+    return code
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _tptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# thin wrappers with the C names
+# ---------------------------------------------------------------------------
+
+def scocg_matrix_from_bsr(nbrows, bdim, rowptr, colidx, vals):
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    colidx = np.ascontiguousarray(colidx, dtype=np.int32)
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    h = _VP()
+    _check(load().scocg_matrix_from_bsr(int(nbrows), int(bdim), _ptr(rowptr), _ptr(colidx), _ptr(vals), C.byref(h)))
+    return h
+
+
+def scocg_matrix_from_csr(n, rowptr, colidx, vals, bdim):
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    colidx = np.ascontiguousarray(colidx, dtype=np.int32)
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    h = _VP()
+    _check(load().scocg_matrix_from_csr(int(n), _ptr(rowptr), _ptr(colidx), _ptr(vals), int(bdim), C.byref(h)))
+    return h
+
+
+def scocg_matrix_free(h):
+    load().scocg_matrix_free(h)
+
+
+def scocg_problem_create(H, S=None):
+    h = _VP()
+    code = _check(load().scocg_problem_create(H, S, C.byref(h)))
+    return h, code
+
+
+def scocg_problem_free(h):
+    load().scocg_problem_free(h)
+
+
+def scocg_options_default(**overrides) -> scocg_options:
+    o = scocg_options()
+    load().scocg_options_default(C.byref(o))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+@dataclass
+class _Spec:
+    struct: scocg_rhs_spec
+    keep: tuple
+
+
+def make_spec(cluster_ptr=None, cluster_atoms=None, out_ptr=None, out_rows=None, full_x=False, order=None):
+    arrs = (
+        None if cluster_ptr is None else np.ascontiguousarray(cluster_ptr, dtype=np.int64),
+        None if cluster_atoms is None else np.ascontiguousarray(cluster_atoms, dtype=np.int32),
+        None if out_ptr is None else np.ascontiguousarray(out_ptr, dtype=np.int64),
+        None if out_rows is None else np.ascontiguousarray(out_rows, dtype=np.int32),
+        None if order is None else np.ascontiguousarray(order, dtype=np.int32),
+    )
+    s = scocg_rhs_spec(_ptr(arrs[0]), _ptr(arrs[1]), OUT_FULL_X if full_x else OUT_SELECTED_G,
+                       _ptr(arrs[2]), _ptr(arrs[3]), _ptr(arrs[4]))
+    return _Spec(s, arrs)
+
+
+def _shifts(z):
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128))
+    return z, z.ctypes.data_as(C.c_void_p)
+
+
+def scocg_plan_create(problem, opt: scocg_options, shifts, rhs_index, spec: _Spec):
+    z, zp = _shifts(shifts)
+    rhs = np.ascontiguousarray(rhs_index, dtype=np.int32)
+    h = _VP()
+    _check(load().scocg_plan_create(problem, C.byref(opt), int(z.size), zp, int(rhs.size), _ptr(rhs),
+                                    C.byref(spec.struct), C.byref(h)))
+    return h
+
+
+def scocg_plan_free(h):
+    load().scocg_plan_free(h)
+
+
+def scocg_plan_out_count(h) -> int:
+    return int(load().scocg_plan_out_count(h))
+
+
+def scocg_plan_out_offsets(h, nrhs) -> np.ndarray:
+    off = np.zeros(nrhs + 1, dtype=np.int64)
+    _check(load().scocg_plan_out_offsets(h, _ptr(off)))
+    return off
+
+
+def scocg_plan_run(h, stream, out, iters=None, status=None, resid=None):
+    """Device buffers are torch CUDA tensors; stream a torch.cuda.Stream or None."""
+    sp = None if stream is None else C.c_void_p(stream.cuda_stream)
+    return _check(load().scocg_plan_run(h, sp, _tptr(out), _tptr(iters), _tptr(status), _tptr(resid)))
+
+
+def scocg_plan_stats(h, nrhs) -> np.ndarray:
+    st = np.zeros((nrhs, NSTAT), dtype=np.int64)
+    _check(load().scocg_plan_stats(h, _ptr(st)))
+    return st
+
+
+def scocg_solve(problem, opt, shifts, rhs_index, spec: _Spec, nout_total):
+    """Host-buffer convenience call; returns (out, iters, status, resid, code)."""
+    z, zp = _shifts(shifts)
+    rhs = np.ascontiguousarray(rhs_index, dtype=np.int32)
+    K, R = z.size, rhs.size
+    out = np.zeros(max(1, nout_total), dtype=np.complex128)
+    iters = np.zeros(R * K, dtype=np.int32)
+    status = np.zeros(R * K, dtype=np.int8)
+    resid = np.zeros(R * K, dtype=np.float64)
+    code = _check(load().scocg_solve(problem, C.byref(opt), int(K), zp, int(R), _ptr(rhs), C.byref(spec.struct),
+                                     _ptr(out), _ptr(iters), _ptr(status), _ptr(resid)))
+    return out[:nout_total], iters.reshape(R, K), status.reshape(R, K), resid.reshape(R, K), code
+
+
+# ---------------------------------------------------------------------------
+# object wrappers
+# ---------------------------------------------------------------------------
+
+class Matrix:
+    def __init__(self, nbrows, bdim, rowptr, colidx, vals):
+        self.h = scocg_matrix_from_bsr(nbrows, bdim, rowptr, colidx, vals)
+
+    @classmethod
+    def from_bsr(cls, A):
+        """From any object with nbrows, bdim, rowptr, colidx, vals attributes."""
+        return cls(A.nbrows, A.bdim, A.rowptr, A.colidx, A.vals)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _LIB is not None:
+            scocg_matrix_free(self.h)
+            self.h = None
+
+
+class Problem:
+    """H and S resident on the current device (S None means S = I)."""
+
+    def __init__(self, H, S=None):
+        self.Hm = Matrix.from_bsr(H)
+        self.Sm = Matrix.from_bsr(S) if S is not None else None
+        self.h, self.code = scocg_problem_create(self.Hm.h, self.Sm.h if self.Sm else None)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _LIB is not None:
+            scocg_problem_free(self.h)
+            self.h = None
+
+
+class Plan:
+    """Everything a solve reads, resident on the device; ``run`` enqueues the solve."""
+
+    def __init__(self, problem: Problem, shifts, rhs, cluster_ptr=None, cluster_atoms=None,
+                 out_ptr=None, out_rows=None, full_x=False, order=None, **options):
+        self.problem = problem
+        self.shifts = np.asarray(shifts, dtype=np.complex128)
+        self.rhs = np.asarray(rhs, dtype=np.int32)
+        self.K, self.nrhs = self.shifts.size, self.rhs.size
+        self.opt = scocg_options_default(**options)
+        self.spec = make_spec(cluster_ptr, cluster_atoms, out_ptr, out_rows, full_x, order)
+        self.h = scocg_plan_create(problem.h, self.opt, self.shifts, self.rhs, self.spec)
+        self.out_count = scocg_plan_out_count(self.h)
+        self.out_offsets = scocg_plan_out_offsets(self.h, self.nrhs)
+
+    def alloc_outputs(self, device="cuda"):
+        import torch
+        R, K = self.nrhs, self.K
+        return dict(
+            out=torch.empty(max(1, self.out_count), dtype=torch.complex128, device=device),
+            iters=torch.empty((R, K), dtype=torch.int32, device=device),
+            status=torch.empty((R, K), dtype=torch.int8, device=device),
+            resid=torch.empty((R, K), dtype=torch.float64, device=device),
+        )
+
+    def run(self, bufs, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        return scocg_plan_run(self.h, stream, bufs["out"], bufs["iters"], bufs["status"], bufs["resid"])
+
+    def stats(self) -> np.ndarray:
+        return scocg_plan_stats(self.h, self.nrhs)
+
+    def solve(self):
+        """Run once and return host results: dict(G=list of [K, nout] arrays, iters, status, resid)."""
+        import torch
+        bufs = self.alloc_outputs()
+        self.run(bufs)
+        torch.cuda.synchronize()
+        out = bufs["out"].cpu().numpy()
+        G = []
+        for r in range(self.nrhs):
+            a, b = self.out_offsets[r] * self.K, self.out_offsets[r + 1] * self.K
+            G.append(out[a:b].reshape(self.K, -1))
+        return dict(G=G, iters=bufs["iters"].cpu().numpy(), status=bufs["status"].cpu().numpy(),
+                    resid=bufs["resid"].cpu().numpy(), stats=self.stats())
+
+    def __del__(self):
+        if getattr(self, "h", None) and _LIB is not None:
+            scocg_plan_free(self.h)
+            self.h = None

@@ -1,0 +1,96 @@
+// Device-side building blocks of the shifted COCG solve (gfx950, wave64).
+//
+// Every function here runs inside ONE workgroup that owns one right-hand
+// side from start to finish: vectors are split over the workgroup's threads
+// by scalar row (row i belongs to thread i mod NT), reductions go through a
+// wave butterfly and then a fixed-order sum over the waves in LDS, so that a
+// run is bitwise reproducible.  The only synchronisation is __syncthreads().
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace scocg {
+
+// ---------------------------------------------------------------------------
+// complex helpers (double2 / float2 hold (re, im))
+// ---------------------------------------------------------------------------
+template <class T> struct vec2;
+template <> struct vec2<double> { using type = double2; };
+template <> struct vec2<float>  { using type = float2; };
+template <class T> using v2 = typename vec2<T>::type;
+
+struct zc { double re, im; };   // FP64 complex scalar in registers
+
+__device__ __forceinline__ zc zmk(double r, double i) { return zc{r, i}; }
+__device__ __forceinline__ zc zadd(zc a, zc b) { return zc{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ zc zsub(zc a, zc b) { return zc{a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ zc zmul(zc a, zc b) {
+    return zc{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// Smith's algorithm for a / b (scaled, avoids overflow for large |b|).
+__device__ __forceinline__ zc zdiv(zc a, zc b) {
+    if (fabs(b.re) >= fabs(b.im)) {
+        double t = b.im / b.re, den = b.re + b.im * t;
+        return zc{(a.re + a.im * t) / den, (a.im - a.re * t) / den};
+    } else {
+        double t = b.re / b.im, den = b.re * t + b.im;
+        return zc{(a.re * t + a.im) / den, (a.im * t - a.re) / den};
+    }
+}
+__device__ __forceinline__ double zabs(zc a) { return hypot(a.re, a.im); }
+__device__ __forceinline__ bool zfinite(zc a) { return isfinite(a.re) && isfinite(a.im); }
+__device__ __forceinline__ bool zzero(zc a) { return a.re == 0.0 && a.im == 0.0; }
+
+template <class T> __device__ __forceinline__ zc ld(const v2<T>* p, int64_t i) {
+    v2<T> v = p[i];
+    return zc{(double)v.x, (double)v.y};
+}
+template <class T> __device__ __forceinline__ void st(v2<T>* p, int64_t i, zc a) {
+    v2<T> v;
+    v.x = (T)a.re;
+    v.y = (T)a.im;
+    p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// block storage: FP64, FP32 or bfloat16 (upper half of an IEEE float)
+// ---------------------------------------------------------------------------
+struct bf16_t { uint16_t bits; };
+__device__ __forceinline__ double bval(const double* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float  bval(const float* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float  bval(const bf16_t* p, int64_t i) {
+    return __uint_as_float(((uint32_t)p[i].bits) << 16);
+}
+
+// ---------------------------------------------------------------------------
+// workgroup reductions (deterministic)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum N doubles over the workgroup; every thread gets the totals.
+// `red` is LDS scratch of at least (NT/64)*N doubles.
+template <int NT, int N>
+__device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int n = 0; n < N; ++n) v[n] = wave_sum(v[n]);
+    if (lane == 0) {
+#pragma unroll
+        for (int n = 0; n < N; ++n) red[w * N + n] = v[n];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        double s = 0.0;
+        for (int q = 0; q < NW; ++q) s += red[q * N + n];
+        v[n] = s;
+    }
+    __syncthreads();
+}
+
+}  // namespace scocg

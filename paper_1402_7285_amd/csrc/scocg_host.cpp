@@ -1,0 +1,827 @@
+// Host side of the scocg C ABI: validation, block-pattern merge, order-N
+// cluster maps, device residency and kernel launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/scocg.h"
+#include "scocg_launch.hpp"
+#include "scocg_params.hpp"
+
+using scocg::KParams;
+using scocg::RhsInfo;
+using scocg::SysInfo;
+
+namespace {
+
+thread_local std::string g_err;
+
+scocg_status fail(scocg_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(call)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            if (e_ == hipErrorOutOfMemory) return fail(SCOCG_E_NOMEM, "%s: %s", #call,       \
+                                                       hipGetErrorString(e_));               \
+            return fail(SCOCG_E_DEVICE, "%s: %s", #call, hipGetErrorString(e_));             \
+        }                                                                                    \
+    } while (0)
+
+template <class T>
+scocg_status dev_upload(T** dst, const T* src, size_t n) {
+    *dst = nullptr;
+    if (n == 0) return SCOCG_OK;
+    HIP_TRY(hipMalloc((void**)dst, n * sizeof(T)));
+    HIP_TRY(hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice));
+    return SCOCG_OK;
+}
+
+template <class T>
+void dev_free(T*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+uint16_t to_bf16(float f) {   // round to nearest even; NaN stays NaN
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// objects
+// ---------------------------------------------------------------------------
+struct scocg_matrix {
+    int64_t nb = 0;
+    int32_t bd = 0;
+    std::vector<int64_t> rowptr;
+    std::vector<int32_t> col;
+    std::vector<double> val;
+};
+
+struct scocg_problem {
+    int device = 0;
+    int64_t nb = 0;
+    int32_t bd = 0;
+    bool has_S = false;
+    bool s_unit_diag = false;
+    std::vector<int64_t> rowptr;   // merged pattern
+    std::vector<int32_t> col;
+    std::vector<double> hH, hS;    // merged values (host copy, for lower-precision copies)
+    double* dH = nullptr;
+    double* dS = nullptr;
+    float* dH32 = nullptr;
+    float* dS32 = nullptr;
+    uint16_t* dHbf = nullptr;
+    uint16_t* dSbf = nullptr;
+    int64_t* dRowptr = nullptr;    // merged pattern on device (global systems)
+    int32_t* dCol = nullptr;
+    int32_t* dIota = nullptr;
+};
+
+struct scocg_plan {
+    scocg_problem* P = nullptr;
+    scocg_options opt{};
+    int32_t K = 0, nrhs = 0, seed0 = 0;
+    int nt = 512, slots = 0, prec = 0;
+    int64_t Mp = 0, slot_bytes = 0, out_count = 0;
+    std::vector<int64_t> out_off;
+    // device arrays owned by the plan
+    double* dz = nullptr;
+    SysInfo* dsys = nullptr;
+    RhsInfo* drhs = nullptr;
+    int64_t* drowptr = nullptr;
+    int32_t* decol = nullptr;
+    int32_t* degid = nullptr;
+    int32_t* doutl = nullptr;
+    int64_t* doutoff = nullptr;
+    int32_t* dorder = nullptr;
+    int32_t* dqueue = nullptr;
+    char* dws = nullptr;
+    int64_t* dstats = nullptr;
+    bool global = true;
+    hipStream_t last_stream = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// matrices
+// ---------------------------------------------------------------------------
+static scocg_status check_bsr(const scocg_matrix& m) {
+    const int64_t nb = m.nb;
+    if (m.rowptr[0] != 0) return fail(SCOCG_E_SHAPE, "rowptr[0] must be 0");
+    for (int64_t a = 0; a < nb; ++a) {
+        if (m.rowptr[a + 1] < m.rowptr[a]) return fail(SCOCG_E_SHAPE, "rowptr decreases at row %lld", (long long)a);
+        for (int64_t e = m.rowptr[a]; e < m.rowptr[a + 1]; ++e) {
+            const int32_t c = m.col[e];
+            if (c < 0 || c >= nb) return fail(SCOCG_E_SHAPE, "colidx %d out of range in row %lld", c, (long long)a);
+            if (e > m.rowptr[a] && m.col[e - 1] >= c)
+                return fail(SCOCG_E_SHAPE, "colidx not strictly ascending in row %lld", (long long)a);
+        }
+    }
+    // exact symmetry: block (a,b) == block (b,a)^T
+    const int bd = m.bd;
+    for (int64_t a = 0; a < nb; ++a) {
+        for (int64_t e = m.rowptr[a]; e < m.rowptr[a + 1]; ++e) {
+            const int64_t b = m.col[e];
+            const int32_t* beg = m.col.data() + m.rowptr[b];
+            const int32_t* end = m.col.data() + m.rowptr[b + 1];
+            const int32_t* f = std::lower_bound(beg, end, (int32_t)a);
+            if (f == end || *f != a)
+                return fail(SCOCG_E_NOT_SYMMETRIC, "block (%lld,%lld) has no partner", (long long)b, (long long)a);
+            const int64_t e2 = f - m.col.data();
+            const double* A = m.val.data() + e * bd * bd;
+            const double* B = m.val.data() + e2 * bd * bd;
+            for (int r = 0; r < bd; ++r)
+                for (int c = 0; c < bd; ++c) {
+                    const double u = A[r * bd + c], v = B[c * bd + r];
+                    if (!(u == v) && !(std::isnan(u) && std::isnan(v)))
+                        return fail(SCOCG_E_NOT_SYMMETRIC, "block (%lld,%lld) != transpose of (%lld,%lld)",
+                                    (long long)a, (long long)b, (long long)b, (long long)a);
+                }
+        }
+    }
+    return SCOCG_OK;
+}
+
+extern "C" const char* scocg_last_error(void) { return g_err.c_str(); }
+extern "C" const char* scocg_version(void) { return "scocg 0.1 (gfx950)"; }
+
+extern "C" scocg_status scocg_matrix_from_bsr(int64_t nbrows, int32_t bdim, const int64_t* rowptr,
+                                              const int32_t* colidx, const double* vals, scocg_matrix** out) {
+    if (!out) return fail(SCOCG_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (nbrows <= 0 || nbrows > INT32_MAX) return fail(SCOCG_E_ARG, "nbrows must be in [1, 2^31)");
+    if (bdim < 1 || bdim > 16) return fail(SCOCG_E_ARG, "bdim must be in [1, 16]");
+    if (!rowptr || !colidx || !vals) return fail(SCOCG_E_ARG, "NULL array");
+    const int64_t nnz = rowptr[nbrows];
+    if (nnz < 0 || nnz > INT32_MAX) return fail(SCOCG_E_SHAPE, "block count out of range");
+    scocg_matrix* m = new (std::nothrow) scocg_matrix;
+    if (!m) return fail(SCOCG_E_NOMEM, "host allocation");
+    try {
+        m->nb = nbrows;
+        m->bd = bdim;
+        m->rowptr.assign(rowptr, rowptr + nbrows + 1);
+        m->col.assign(colidx, colidx + nnz);
+        m->val.assign(vals, vals + nnz * (int64_t)bdim * bdim);
+    } catch (...) {
+        delete m;
+        return fail(SCOCG_E_NOMEM, "host allocation");
+    }
+    const scocg_status st = check_bsr(*m);
+    if (st != SCOCG_OK) {
+        delete m;
+        return st;
+    }
+    *out = m;
+    return SCOCG_OK;
+}
+
+extern "C" scocg_status scocg_matrix_from_csr(int64_t n, const int64_t* rowptr, const int32_t* colidx,
+                                              const double* vals, int32_t bdim, scocg_matrix** out) {
+    if (!out) return fail(SCOCG_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (bdim < 1 || bdim > 16 || n <= 0 || n % bdim) return fail(SCOCG_E_ARG, "n must be a positive multiple of bdim");
+    if (!rowptr || !colidx || !vals) return fail(SCOCG_E_ARG, "NULL array");
+    const int64_t nb = n / bdim;
+    std::vector<int64_t> brp(nb + 1, 0);
+    std::vector<std::vector<int32_t>> cols(nb);
+    for (int64_t i = 0; i < n; ++i) {
+        if (rowptr[i + 1] < rowptr[i]) return fail(SCOCG_E_SHAPE, "rowptr decreases");
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            if (colidx[e] < 0 || colidx[e] >= n) return fail(SCOCG_E_SHAPE, "column out of range");
+            if (e > rowptr[i] && colidx[e - 1] >= colidx[e]) return fail(SCOCG_E_SHAPE, "columns not ascending");
+            cols[i / bdim].push_back(colidx[e] / bdim);
+        }
+    }
+    std::vector<int32_t> bcol;
+    for (int64_t a = 0; a < nb; ++a) {
+        auto& c = cols[a];
+        std::sort(c.begin(), c.end());
+        c.erase(std::unique(c.begin(), c.end()), c.end());
+        brp[a + 1] = brp[a] + (int64_t)c.size();
+        bcol.insert(bcol.end(), c.begin(), c.end());
+    }
+    std::vector<double> bval((size_t)brp[nb] * bdim * bdim, 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t a = i / bdim, r = i % bdim;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            const int32_t b = colidx[e] / bdim, c = colidx[e] % bdim;
+            const int32_t* beg = bcol.data() + brp[a];
+            const int64_t pos = std::lower_bound(beg, (const int32_t*)bcol.data() + brp[a + 1], b) - bcol.data();
+            bval[(pos * bdim + r) * bdim + c] = vals[e];
+        }
+    }
+    return scocg_matrix_from_bsr(nb, bdim, brp.data(), bcol.data(), bval.data(), out);
+}
+
+extern "C" void scocg_matrix_free(scocg_matrix* m) { delete m; }
+
+// ---------------------------------------------------------------------------
+// problem
+// ---------------------------------------------------------------------------
+extern "C" void scocg_problem_free(scocg_problem* p) {
+    if (!p) return;
+    (void)hipSetDevice(p->device);
+    dev_free(p->dH);
+    dev_free(p->dS);
+    dev_free(p->dH32);
+    dev_free(p->dS32);
+    dev_free(p->dHbf);
+    dev_free(p->dSbf);
+    dev_free(p->dRowptr);
+    dev_free(p->dCol);
+    dev_free(p->dIota);
+    delete p;
+}
+
+extern "C" scocg_status scocg_problem_create(const scocg_matrix* H, const scocg_matrix* S, scocg_problem** out) {
+    if (!out) return fail(SCOCG_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!H) return fail(SCOCG_E_ARG, "H is NULL");
+    if (S && (S->nb != H->nb || S->bd != H->bd)) return fail(SCOCG_E_SHAPE, "H and S differ in shape");
+    scocg_problem* p = new (std::nothrow) scocg_problem;
+    if (!p) return fail(SCOCG_E_NOMEM, "host allocation");
+    scocg_status st = SCOCG_OK;
+    try {
+        HIP_TRY(hipGetDevice(&p->device));
+        p->nb = H->nb;
+        p->bd = H->bd;
+        p->has_S = S != nullptr;
+        const int bd = p->bd, bb = bd * bd;
+        p->rowptr.assign(p->nb + 1, 0);
+        // merged pattern: per row, the sorted union of H's and S's columns
+        for (int64_t a = 0; a < p->nb; ++a) {
+            int64_t i = H->rowptr[a], ie = H->rowptr[a + 1];
+            int64_t j = S ? S->rowptr[a] : 0, je = S ? S->rowptr[a + 1] : 0;
+            while (i < ie || j < je) {
+                int32_t c;
+                const bool th = i < ie && (j >= je || H->col[i] <= S->col[j]);
+                const bool ts = j < je && (i >= ie || S->col[j] <= H->col[i]);
+                c = th ? H->col[i] : S->col[j];
+                p->col.push_back(c);
+                for (int t = 0; t < bb; ++t) p->hH.push_back(th ? H->val[i * bb + t] : 0.0);
+                if (S)
+                    for (int t = 0; t < bb; ++t) p->hS.push_back(ts ? S->val[j * bb + t] : 0.0);
+                if (th) ++i;
+                if (ts) ++j;
+            }
+            p->rowptr[a + 1] = (int64_t)p->col.size();
+        }
+        if (p->col.size() > (size_t)INT32_MAX) {
+            scocg_problem_free(p);
+            return fail(SCOCG_E_SHAPE, "too many blocks");
+        }
+        const int64_t nblk = (int64_t)p->col.size();
+        // S diagonal: unit? (only needs SPD; a unit diagonal is the LCAO norm)
+        if (S) {
+            bool unit = true, unit_diag_elems = true;
+            for (int64_t a = 0; a < p->nb; ++a) {
+                const int32_t* beg = p->col.data() + p->rowptr[a];
+                const int64_t e = std::lower_bound(beg, (const int32_t*)p->col.data() + p->rowptr[a + 1], (int32_t)a) - p->col.data();
+                if (e >= p->rowptr[a + 1] || p->col[e] != a) {
+                    unit = unit_diag_elems = false;
+                    break;
+                }
+                for (int r = 0; r < bd; ++r)
+                    for (int c = 0; c < bd; ++c) {
+                        const double v = p->hS[e * bb + r * bd + c];
+                        if (v != (r == c ? 1.0 : 0.0)) unit = false;
+                        if (r == c && v != 1.0) unit_diag_elems = false;
+                    }
+            }
+            p->s_unit_diag = unit;
+            if (!unit_diag_elems) st = SCOCG_W_S_DIAG;
+        }
+        scocg_status e;
+        if ((e = dev_upload(&p->dH, p->hH.data(), p->hH.size())) != SCOCG_OK) { scocg_problem_free(p); return e; }
+        if (S && (e = dev_upload(&p->dS, p->hS.data(), p->hS.size())) != SCOCG_OK) { scocg_problem_free(p); return e; }
+        if ((e = dev_upload(&p->dRowptr, p->rowptr.data(), p->rowptr.size())) != SCOCG_OK) { scocg_problem_free(p); return e; }
+        if ((e = dev_upload(&p->dCol, p->col.data(), p->col.size())) != SCOCG_OK) { scocg_problem_free(p); return e; }
+        std::vector<int32_t> iota(nblk);
+        for (int64_t t = 0; t < nblk; ++t) iota[t] = (int32_t)t;
+        if ((e = dev_upload(&p->dIota, iota.data(), iota.size())) != SCOCG_OK) { scocg_problem_free(p); return e; }
+    } catch (const std::bad_alloc&) {
+        scocg_problem_free(p);
+        return fail(SCOCG_E_NOMEM, "host allocation");
+    }
+    *out = p;
+    if (st != SCOCG_OK) fail(st, "S has a diagonal element different from 1");
+    return st;
+}
+
+static scocg_status ensure_lowp(scocg_problem* p, int prec) {
+    if (prec == SCOCG_FP32 && !p->dH32) {
+        std::vector<float> h(p->hH.begin(), p->hH.end());
+        scocg_status e = dev_upload(&p->dH32, h.data(), h.size());
+        if (e) return e;
+        if (p->has_S) {
+            std::vector<float> s(p->hS.begin(), p->hS.end());
+            if ((e = dev_upload(&p->dS32, s.data(), s.size()))) return e;
+        }
+    }
+    if (prec == SCOCG_FP32_BF16 && !p->dHbf) {
+        std::vector<uint16_t> h(p->hH.size());
+        for (size_t i = 0; i < h.size(); ++i) h[i] = to_bf16((float)p->hH[i]);
+        scocg_status e = dev_upload(&p->dHbf, h.data(), h.size());
+        if (e) return e;
+        if (p->has_S) {
+            std::vector<uint16_t> s(p->hS.size());
+            for (size_t i = 0; i < s.size(); ++i) s[i] = to_bf16((float)p->hS[i]);
+            if ((e = dev_upload(&p->dSbf, s.data(), s.size()))) return e;
+        }
+    }
+    return SCOCG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// options
+// ---------------------------------------------------------------------------
+extern "C" void scocg_options_default(scocg_options* o) {
+    if (!o) return;
+    o->tol = 1e-10;
+    o->maxiter = 0;
+    o->precision = SCOCG_FP64;
+    o->replace_every = 20;
+    o->inner_maxiter = 1000;
+    o->inner_tol = 1e-13;
+    o->inner_tol_lo = 1e-6;
+    o->seed_index = -1;
+    o->threads = 0;
+    o->slots = 0;
+    o->audit = 1;
+}
+
+// Initial seed: smallest |Im z|, then Re z closest to the median of Re z
+// (mean of the two middle values for an even count), then lowest index.
+static int initial_seed(const scocg_z* z, int K) {
+    std::vector<double> E(K);
+    for (int k = 0; k < K; ++k) E[k] = z[k].re;
+    std::sort(E.begin(), E.end());
+    const double med = (K % 2) ? E[K / 2] : (E[K / 2 - 1] + E[K / 2]) / 2.0;
+    int best = 0;
+    for (int k = 1; k < K; ++k) {
+        const double ai = std::fabs(z[k].im), bi = std::fabs(z[best].im);
+        const double ar = std::fabs(z[k].re - med), br = std::fabs(z[best].re - med);
+        if (ai < bi || (ai == bi && ar < br)) best = k;
+    }
+    return best;
+}
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+extern "C" void scocg_plan_free(scocg_plan* pl) {
+    if (!pl) return;
+    (void)hipSetDevice(pl->P->device);
+    if (pl->last_stream) (void)hipStreamSynchronize(pl->last_stream);
+    else (void)hipDeviceSynchronize();
+    dev_free(pl->dz);
+    dev_free(pl->dsys);
+    dev_free(pl->drhs);
+    if (!pl->global) {
+        dev_free(pl->drowptr);
+        dev_free(pl->decol);
+        dev_free(pl->degid);
+    }
+    dev_free(pl->doutl);
+    dev_free(pl->doutoff);
+    dev_free(pl->dorder);
+    dev_free(pl->dqueue);
+    dev_free(pl->dws);
+    dev_free(pl->dstats);
+    delete pl;
+}
+
+namespace {
+
+struct HostMaps {
+    std::vector<SysInfo> sys;
+    std::vector<RhsInfo> rhs;
+    std::vector<int64_t> rowptr;
+    std::vector<int32_t> ecol, egid, outl;
+    std::vector<int64_t> outoff;
+    int64_t maxM = 0;
+};
+
+template <class F>
+void parallel_for(int64_t n, F f) {
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (n < 64) nth = 1;
+    std::vector<std::thread> th;
+    std::atomic<int64_t> next{0};
+    auto body = [&]() {
+        for (;;) {
+            const int64_t i = next.fetch_add(16);
+            if (i >= n) break;
+            for (int64_t t = i; t < std::min(n, i + 16); ++t) f(t);
+        }
+    };
+    for (unsigned t = 1; t < nth; ++t) th.emplace_back(body);
+    body();
+    for (auto& t : th) t.join();
+}
+
+scocg_status build_maps(const scocg_problem* P, int32_t nrhs, const int32_t* rhs_index,
+                        const scocg_rhs_spec* spec, HostMaps& hm) {
+    const int bd = P->bd;
+    const int64_t nb = P->nb, M = nb * bd;
+    const bool cluster = spec && spec->cluster_ptr;
+    const bool full = spec && spec->out_mode == SCOCG_OUT_FULL_X;
+    if (spec && spec->out_mode != SCOCG_OUT_FULL_X && spec->out_mode != SCOCG_OUT_SELECTED_G)
+        return fail(SCOCG_E_ARG, "unknown out_mode %d", spec->out_mode);
+    if (!full && (!spec || !spec->out_ptr || !spec->out_rows))
+        return fail(SCOCG_E_ARG, "SELECTED_G needs out_ptr and out_rows");
+    if (cluster && !spec->cluster_atoms) return fail(SCOCG_E_ARG, "cluster_atoms is NULL");
+    for (int32_t r = 0; r < nrhs; ++r)
+        if (rhs_index[r] < 0 || rhs_index[r] >= M) return fail(SCOCG_E_ARG, "rhs_index[%d] out of range", r);
+    if (!full) {
+        if (spec->out_ptr[0] != 0) return fail(SCOCG_E_ARG, "out_ptr[0] must be 0");
+        for (int32_t r = 0; r < nrhs; ++r)
+            if (spec->out_ptr[r + 1] < spec->out_ptr[r]) return fail(SCOCG_E_ARG, "out_ptr decreases");
+    }
+    if (cluster) {
+        if (spec->cluster_ptr[0] != 0) return fail(SCOCG_E_ARG, "cluster_ptr[0] must be 0");
+        for (int32_t r = 0; r < nrhs; ++r) {
+            const int64_t c0 = spec->cluster_ptr[r], c1 = spec->cluster_ptr[r + 1];
+            if (c1 <= c0) return fail(SCOCG_E_ARG, "cluster of RHS %d is empty", r);
+            if ((c1 - c0) * bd > INT32_MAX / 2) return fail(SCOCG_E_ARG, "cluster too large");
+            for (int64_t t = c0; t < c1; ++t) {
+                const int32_t a = spec->cluster_atoms[t];
+                if (a < 0 || a >= nb) return fail(SCOCG_E_ARG, "cluster atom out of range (RHS %d)", r);
+                if (t > c0 && spec->cluster_atoms[t - 1] >= a)
+                    return fail(SCOCG_E_ARG, "cluster atoms of RHS %d not strictly ascending", r);
+            }
+        }
+    }
+    hm.rhs.resize(nrhs);
+    hm.outoff.assign(nrhs + 1, 0);
+    if (!cluster) {
+        SysInfo s{0, 0, (int32_t)nb, 0};
+        hm.sys.push_back(s);
+        hm.maxM = M;
+        for (int32_t r = 0; r < nrhs; ++r) {
+            RhsInfo& ri = hm.rhs[r];
+            ri.sys = 0;
+            ri.b_local = rhs_index[r];
+            ri.full_x = full ? 1 : 0;
+            if (full) {
+                ri.out_base = 0;
+                ri.nout = (int32_t)M;
+            } else {
+                ri.out_base = spec->out_ptr[r];
+                ri.nout = (int32_t)(spec->out_ptr[r + 1] - spec->out_ptr[r]);
+                for (int64_t t = spec->out_ptr[r]; t < spec->out_ptr[r + 1]; ++t)
+                    if (spec->out_rows[t] < 0 || spec->out_rows[t] >= M)
+                        return fail(SCOCG_E_ARG, "out row out of range (RHS %d)", r);
+            }
+            hm.outoff[r + 1] = hm.outoff[r] + ri.nout;
+        }
+        if (!full) hm.outl.assign(spec->out_rows, spec->out_rows + spec->out_ptr[nrhs]);
+        return SCOCG_OK;
+    }
+    // ---- order-N clusters: principal submatrix on each RHS's atoms
+    std::vector<int64_t> ecount(nrhs, 0);
+    std::atomic<int> bad{-1};
+    std::atomic<int> badkind{0};
+    const int64_t* rp = P->rowptr.data();
+    const int32_t* cl = P->col.data();
+    auto count_fn = [&](int64_t r) {
+        const int64_t c0 = spec->cluster_ptr[r], c1 = spec->cluster_ptr[r + 1];
+        const int32_t* at = spec->cluster_atoms + c0;
+        const int64_t n = c1 - c0;
+        int64_t cnt = 0;
+        for (int64_t t = 0; t < n; ++t) {
+            const int32_t a = at[t];
+            for (int64_t e = rp[a]; e < rp[a + 1]; ++e)
+                if (std::binary_search(at, at + n, cl[e])) ++cnt;
+        }
+        ecount[r] = cnt;
+        const int32_t ja = rhs_index[r] / bd;
+        if (!std::binary_search(at, at + n, ja)) { bad = (int)r; badkind = 1; }
+        if (!full) {
+            for (int64_t t = spec->out_ptr[r]; t < spec->out_ptr[r + 1]; ++t) {
+                const int32_t o = spec->out_rows[t];
+                if (o < 0 || o >= M || !std::binary_search(at, at + n, o / bd)) { bad = (int)r; badkind = 2; }
+            }
+        }
+    };
+    parallel_for(nrhs, count_fn);
+    if (bad >= 0)
+        return fail(SCOCG_E_ARG, badkind == 1 ? "RHS %d: its orbital's atom is not in its cluster"
+                                              : "RHS %d: an out row is not in its cluster", (int)bad);
+    hm.sys.resize(nrhs);
+    int64_t rbase = 0, ebase = 0, obase = 0;
+    for (int32_t r = 0; r < nrhs; ++r) {
+        const int64_t n = spec->cluster_ptr[r + 1] - spec->cluster_ptr[r];
+        hm.sys[r] = SysInfo{rbase, ebase, (int32_t)n, 0};
+        rbase += n + 1;
+        ebase += ecount[r];
+        RhsInfo& ri = hm.rhs[r];
+        ri.sys = r;
+        ri.full_x = full ? 1 : 0;
+        ri.nout = full ? (int32_t)(n * bd) : (int32_t)(spec->out_ptr[r + 1] - spec->out_ptr[r]);
+        ri.out_base = obase;
+        if (!full) obase += ri.nout;
+        hm.outoff[r + 1] = hm.outoff[r] + ri.nout;
+        hm.maxM = std::max<int64_t>(hm.maxM, n * bd);
+    }
+    hm.rowptr.assign(rbase, 0);
+    hm.ecol.assign(ebase, 0);
+    hm.egid.assign(ebase, 0);
+    hm.outl.assign(obase, 0);
+    auto fill_fn = [&](int64_t r) {
+        const int64_t c0 = spec->cluster_ptr[r], c1 = spec->cluster_ptr[r + 1];
+        const int32_t* at = spec->cluster_atoms + c0;
+        const int64_t n = c1 - c0;
+        int64_t* rowp = hm.rowptr.data() + hm.sys[r].row_base;
+        int32_t* ec = hm.ecol.data() + hm.sys[r].ent_base;
+        int32_t* eg = hm.egid.data() + hm.sys[r].ent_base;
+        int64_t cnt = 0;
+        rowp[0] = 0;
+        for (int64_t t = 0; t < n; ++t) {
+            const int32_t a = at[t];
+            for (int64_t e = rp[a]; e < rp[a + 1]; ++e) {
+                const int32_t* f = std::lower_bound(at, at + n, cl[e]);
+                if (f != at + n && *f == cl[e]) {
+                    ec[cnt] = (int32_t)(f - at);
+                    eg[cnt] = (int32_t)e;
+                    ++cnt;
+                }
+            }
+            rowp[t + 1] = cnt;
+        }
+        const int32_t j = rhs_index[r];
+        hm.rhs[r].b_local = (int32_t)((std::lower_bound(at, at + n, j / bd) - at) * bd + j % bd);
+        if (!full) {
+            int32_t* ol = hm.outl.data() + hm.rhs[r].out_base;
+            for (int64_t t = spec->out_ptr[r]; t < spec->out_ptr[r + 1]; ++t) {
+                const int32_t o = spec->out_rows[t];
+                ol[t - spec->out_ptr[r]] = (int32_t)((std::lower_bound(at, at + n, o / bd) - at) * bd + o % bd);
+            }
+        }
+    };
+    parallel_for(nrhs, fill_fn);
+    return SCOCG_OK;
+}
+
+}  // namespace
+
+extern "C" scocg_status scocg_plan_create(scocg_problem* P, const scocg_options* opt_in, int32_t nshift,
+                                          const scocg_z* shifts, int32_t nrhs, const int32_t* rhs_index,
+                                          const scocg_rhs_spec* spec, scocg_plan** out) {
+    if (!out) return fail(SCOCG_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!P) return fail(SCOCG_E_ARG, "problem is NULL");
+    scocg_options opt;
+    if (opt_in) opt = *opt_in; else scocg_options_default(&opt);
+    if (!(opt.tol > 0.0)) return fail(SCOCG_E_ARG, "tol must be > 0");
+    if (opt.maxiter < 0 || opt.inner_maxiter < 0) return fail(SCOCG_E_ARG, "negative iteration cap");
+    if (opt.precision < SCOCG_FP64 || opt.precision > SCOCG_FP32_BF16) return fail(SCOCG_E_ARG, "unknown precision");
+    if (!(opt.inner_tol > 0.0) || !(opt.inner_tol_lo > 0.0)) return fail(SCOCG_E_ARG, "inner tolerances must be > 0");
+    if (opt.threads != 0 && opt.threads != 256 && opt.threads != 512 && opt.threads != 1024)
+        return fail(SCOCG_E_ARG, "threads must be 0, 256, 512 or 1024");
+    if (opt.slots < 0) return fail(SCOCG_E_ARG, "slots must be >= 0");
+    if (nshift < 1 || nshift > 512) return fail(nshift < 1 ? SCOCG_E_ARG : SCOCG_E_UNSUPPORTED, "nshift must be in [1, 512]");
+    if (!shifts) return fail(SCOCG_E_ARG, "shifts is NULL");
+    for (int k = 0; k < nshift; ++k)
+        if (!std::isfinite(shifts[k].re) || !std::isfinite(shifts[k].im)) return fail(SCOCG_E_ARG, "shift %d not finite", k);
+    if (nrhs < 0 || (nrhs > 0 && !rhs_index)) return fail(SCOCG_E_ARG, "bad RHS list");
+    if (opt.seed_index < -1 || opt.seed_index >= nshift) return fail(SCOCG_E_ARG, "seed_index out of range");
+    if (!scocg::supported_bdim(P->bd)) return fail(SCOCG_E_UNSUPPORTED, "block size %d not compiled in", P->bd);
+    if (spec && spec->order) {
+        std::vector<char> seen(nrhs, 0);
+        for (int32_t r = 0; r < nrhs; ++r) {
+            const int32_t o = spec->order[r];
+            if (o < 0 || o >= nrhs || seen[o]) return fail(SCOCG_E_ARG, "order is not a permutation");
+            seen[o] = 1;
+        }
+    }
+    HIP_TRY(hipSetDevice(P->device));
+    HostMaps hm;
+    scocg_status st;
+    try {
+        st = build_maps(P, nrhs, rhs_index, spec, hm);
+    } catch (const std::bad_alloc&) {
+        return fail(SCOCG_E_NOMEM, "host allocation");
+    }
+    if (st != SCOCG_OK) return st;
+    if ((st = ensure_lowp(P, opt.precision)) != SCOCG_OK) return st;
+
+    scocg_plan* pl = new (std::nothrow) scocg_plan;
+    if (!pl) return fail(SCOCG_E_NOMEM, "host allocation");
+    pl->P = P;
+    pl->opt = opt;
+    pl->K = nshift;
+    pl->nrhs = nrhs;
+    pl->prec = opt.precision;
+    pl->seed0 = opt.seed_index >= 0 ? opt.seed_index : initial_seed(shifts, nshift);
+    pl->global = !(spec && spec->cluster_ptr);
+    pl->out_off = hm.outoff;
+    pl->out_count = hm.outoff[nrhs] * (int64_t)nshift;
+    pl->nt = opt.threads ? opt.threads : 512;
+    pl->Mp = std::max<int64_t>(64, (hm.maxM + 63) / 64 * 64);
+    const int64_t vsz = opt.precision == SCOCG_FP64 ? 16 : 8;
+    pl->slot_bytes = ((2 * (int64_t)nshift + 6) * pl->Mp * vsz + 255) / 256 * 256;
+
+    auto bail = [&](scocg_status e) { scocg_plan_free(pl); return e; };
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess || cus <= 0) cus = 256;
+    const size_t lds = scocg::solver_lds_bytes(nshift, pl->nt);
+    if (lds > 160 * 1024) return bail(fail(SCOCG_E_UNSUPPORTED, "too many shifts for LDS"));
+    int per_cu = std::max(1, 2048 / pl->nt);
+    per_cu = std::min<int>(per_cu, (int)std::max<size_t>(1, (160 * 1024) / lds));
+    per_cu = std::min(per_cu, 2);
+    int slots = opt.slots ? opt.slots : cus * per_cu;
+    slots = std::max(1, std::min(slots, std::max(1, nrhs)));
+    size_t freeb = 0, totb = 0;
+    if (hipMemGetInfo(&freeb, &totb) == hipSuccess && freeb > 0) {
+        const int64_t cap = (int64_t)(0.8 * (double)freeb) / std::max<int64_t>(1, pl->slot_bytes);
+        if (cap < 1) return bail(fail(SCOCG_E_NOMEM, "one workgroup slot (%lld bytes) exceeds free memory",
+                                      (long long)pl->slot_bytes));
+        slots = (int)std::min<int64_t>(slots, cap);
+    }
+    pl->slots = slots;
+
+    std::vector<double> zz(2 * nshift);
+    for (int k = 0; k < nshift; ++k) {
+        zz[2 * k] = shifts[k].re;
+        zz[2 * k + 1] = shifts[k].im;
+    }
+    std::vector<int32_t> order(nrhs);
+    for (int32_t r = 0; r < nrhs; ++r) order[r] = (spec && spec->order) ? spec->order[r] : r;
+    if ((st = dev_upload(&pl->dz, zz.data(), zz.size()))) return bail(st);
+    if ((st = dev_upload(&pl->dsys, hm.sys.data(), hm.sys.size()))) return bail(st);
+    if ((st = dev_upload(&pl->drhs, hm.rhs.data(), hm.rhs.size()))) return bail(st);
+    if (pl->global) {
+        pl->drowptr = P->dRowptr;
+        pl->decol = P->dCol;
+        pl->degid = P->dIota;
+    } else {
+        if ((st = dev_upload(&pl->drowptr, hm.rowptr.data(), hm.rowptr.size()))) return bail(st);
+        if ((st = dev_upload(&pl->decol, hm.ecol.data(), hm.ecol.size()))) return bail(st);
+        if ((st = dev_upload(&pl->degid, hm.egid.data(), hm.egid.size()))) return bail(st);
+    }
+    if ((st = dev_upload(&pl->doutl, hm.outl.data(), hm.outl.size()))) return bail(st);
+    if ((st = dev_upload(&pl->doutoff, hm.outoff.data(), hm.outoff.size()))) return bail(st);
+    if ((st = dev_upload(&pl->dorder, order.data(), order.size()))) return bail(st);
+    if (hipMalloc((void**)&pl->dqueue, sizeof(int32_t)) != hipSuccess) return bail(fail(SCOCG_E_NOMEM, "queue"));
+    if (nrhs > 0) {
+        if (hipMalloc((void**)&pl->dws, (size_t)pl->slot_bytes * slots) != hipSuccess)
+            return bail(fail(SCOCG_E_NOMEM, "workspace of %lld bytes", (long long)pl->slot_bytes * slots));
+        if (hipMalloc((void**)&pl->dstats, sizeof(int64_t) * scocg::NSTAT * nrhs) != hipSuccess)
+            return bail(fail(SCOCG_E_NOMEM, "stats"));
+    }
+    *out = pl;
+    return SCOCG_OK;
+}
+
+extern "C" int64_t scocg_plan_out_count(const scocg_plan* pl) { return pl ? pl->out_count : -1; }
+
+extern "C" scocg_status scocg_plan_out_offsets(const scocg_plan* pl, int64_t* offsets) {
+    if (!pl || !offsets) return fail(SCOCG_E_ARG, "NULL argument");
+    std::memcpy(offsets, pl->out_off.data(), sizeof(int64_t) * pl->out_off.size());
+    return SCOCG_OK;
+}
+
+extern "C" scocg_status scocg_plan_run(scocg_plan* pl, void* stream, scocg_z* out, int32_t* iters,
+                                       int8_t* status, double* resid) {
+    if (!pl) return fail(SCOCG_E_ARG, "plan is NULL");
+    if (!out && pl->out_count > 0) return fail(SCOCG_E_ARG, "out is NULL");
+    if (pl->nrhs == 0) return SCOCG_OK;
+    HIP_TRY(hipSetDevice(pl->P->device));
+    hipStream_t st = (hipStream_t)stream;
+    pl->last_stream = st;
+    const scocg_problem* P = pl->P;
+    KParams k{};
+    if (pl->prec == SCOCG_FP64) {
+        k.Hv = P->dH;
+        k.Sv = P->dS;
+    } else if (pl->prec == SCOCG_FP32) {
+        k.Hv = P->dH32;
+        k.Sv = P->dS32;
+    } else {
+        k.Hv = P->dHbf;
+        k.Sv = P->dSbf;
+    }
+    k.Hv64 = P->dH;
+    k.Sv64 = P->dS;
+    k.rowptr_l = pl->drowptr;
+    k.ecol = pl->decol;
+    k.egid = pl->degid;
+    k.sys = pl->dsys;
+    k.rhs = pl->drhs;
+    k.out_local = pl->doutl;
+    k.out_off = pl->doutoff;
+    k.order = pl->dorder;
+    k.z = pl->dz;
+    k.nrhs = pl->nrhs;
+    k.K = pl->K;
+    k.seed0 = pl->seed0;
+    k.maxiter = pl->opt.maxiter;
+    k.tol = pl->opt.tol;
+    k.inner_tol = pl->opt.inner_tol;
+    k.inner_tol_lo = pl->opt.inner_tol_lo;
+    k.inner_maxiter = pl->opt.inner_maxiter;
+    k.replace_every = pl->opt.replace_every;
+    k.audit = pl->opt.audit;
+    k.s_unit_diag = P->s_unit_diag ? 1 : 0;
+    k.queue = pl->dqueue;
+    k.ws = pl->dws;
+    k.slot_bytes = pl->slot_bytes;
+    k.Mp = pl->Mp;
+    k.out = (double*)out;
+    k.iters = iters;
+    k.status = status;
+    k.resid = resid;
+    k.stats = pl->dstats;
+    (void)hipGetLastError();   // drop any error another caller left on this thread
+    HIP_TRY(scocg::launch_fill_i32(pl->dqueue, 0, 1, st));
+    HIP_TRY(scocg::launch_solver(k, P->bd, pl->prec, !P->has_S, pl->nt, pl->slots, st));
+    return SCOCG_OK;
+}
+
+extern "C" scocg_status scocg_plan_stats(scocg_plan* pl, int64_t* stats) {
+    if (!pl || !stats) return fail(SCOCG_E_ARG, "NULL argument");
+    if (pl->nrhs == 0) return SCOCG_OK;
+    HIP_TRY(hipSetDevice(pl->P->device));
+    if (pl->last_stream) HIP_TRY(hipStreamSynchronize(pl->last_stream));
+    else HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(stats, pl->dstats, sizeof(int64_t) * scocg::NSTAT * pl->nrhs, hipMemcpyDeviceToHost));
+    return SCOCG_OK;
+}
+
+extern "C" scocg_status scocg_solve(scocg_problem* P, const scocg_options* opt, int32_t nshift,
+                                    const scocg_z* shifts, int32_t nrhs, const int32_t* rhs_index,
+                                    const scocg_rhs_spec* spec, scocg_z* out, int32_t* iters, int8_t* status,
+                                    double* resid) {
+    scocg_plan* pl = nullptr;
+    scocg_status st = scocg_plan_create(P, opt, nshift, shifts, nrhs, rhs_index, spec, &pl);
+    if (st < 0) return st;
+    if (nrhs == 0) {
+        scocg_plan_free(pl);
+        return SCOCG_OK;
+    }
+    if (!out) {
+        scocg_plan_free(pl);
+        return fail(SCOCG_E_ARG, "out is NULL");
+    }
+    const size_t nk = (size_t)nrhs * nshift;
+    scocg_z* dout = nullptr;
+    int32_t* dit = nullptr;
+    int8_t* dst = nullptr;
+    double* dres = nullptr;
+    auto cleanup = [&]() {
+        dev_free(dout);
+        dev_free(dit);
+        dev_free(dst);
+        dev_free(dres);
+        scocg_plan_free(pl);
+    };
+    if (hipMalloc((void**)&dout, sizeof(scocg_z) * std::max<int64_t>(1, pl->out_count)) != hipSuccess ||
+        hipMalloc((void**)&dit, sizeof(int32_t) * nk) != hipSuccess ||
+        hipMalloc((void**)&dst, nk) != hipSuccess || hipMalloc((void**)&dres, sizeof(double) * nk) != hipSuccess) {
+        cleanup();
+        return fail(SCOCG_E_NOMEM, "output buffers");
+    }
+    st = scocg_plan_run(pl, nullptr, dout, dit, dst, dres);
+    if (st == SCOCG_OK) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e == hipSuccess) e = hipMemcpy(out, dout, sizeof(scocg_z) * pl->out_count, hipMemcpyDeviceToHost);
+        std::vector<int8_t> hst(nk);
+        if (e == hipSuccess) e = hipMemcpy(hst.data(), dst, nk, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && iters) e = hipMemcpy(iters, dit, sizeof(int32_t) * nk, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && resid) e = hipMemcpy(resid, dres, sizeof(double) * nk, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            cleanup();
+            return fail(SCOCG_E_DEVICE, "solve: %s", hipGetErrorString(e));
+        }
+        if (status) std::memcpy(status, hst.data(), nk);
+        for (size_t t = 0; t < nk; ++t)
+            if (hst[t] != SCOCG_CONVERGED) { st = SCOCG_W_PARTIAL; break; }
+    }
+    cleanup();
+    return st;
+}

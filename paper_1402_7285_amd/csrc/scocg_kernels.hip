@@ -1,0 +1,610 @@
+// Persistent shifted-COCG solver kernel for gfx950.
+//
+// One workgroup owns one right-hand side b = e_j at a time and runs the
+// whole method for it (the generalized shifted COCG of Sec. 3, item (i), for
+// (z_k S - H) x = b, Sec. 3 Eq. 2), then pops the next RHS from an atomic
+// work queue.  Per outer iteration n, for seed shift s:
+//
+//   q      = (z_s S - H) p_s          fused H and S pass over the local BSR
+//   mu     = p_s^T q                  unconjugated (complex-symmetric form)
+//   alpha  = gamma / mu;  rho -= alpha q
+//   r      = S^{-1} rho               Hermitian CG on the real SPD S (S = I: r = rho)
+//   gamma' = rho^T r, nu = ||rho||_2, beta = gamma'/gamma
+//   for every unconverged shift k (FP64 scalars, one thread per shift):
+//     pi_{n+1} = (1 + alpha (z_k - z_s)) pi_n + (beta_{n-1} alpha / alpha_{n-1}) (pi_n - pi_{n-1})
+//     alpha_k = (pi_n/pi_{n+1}) alpha,  beta_k = (pi_n/pi_{n+1})^2 beta
+//     converged when nu / |pi_{n+1}| < tol ||b||
+//   x_k += alpha_k p_k;  p_k = r / pi_{n+1} + beta_k p_k      (the HBM-bound sweep)
+//   if the seed converged: switch to the unconverged shift with the smallest
+//   |pi| and rescale rho, r, gamma, alpha, beta and every pi by its pi.
+//
+// The recurrences follow from the collinearity of the shifted residuals in
+// the common Krylov space (r_k = r / pi_k with pi_k = R_n(z_s - z_k) for the
+// seed's residual polynomial R_n); they are written out in the library's
+// design notes.  No grid-wide synchronisation is used anywhere.
+#include <hip/hip_runtime.h>
+
+#include "scocg_device.hpp"
+#include "scocg_params.hpp"
+
+namespace scocg {
+
+enum { ST_CONVERGED = 0, ST_MAXITER = 1, ST_BREAKDOWN = 2, ST_NONFINITE = 3 };
+
+// A local system seen from one workgroup.
+struct Sys {
+    const int64_t* rowptr;
+    const int32_t* ecol;
+    const int32_t* egid;
+    int nrows;
+    int M;
+};
+
+// LDS layout for K shifts (dynamic shared memory).
+struct Lds {
+    zc* pi;
+    zc* piold;
+    zc* ca;
+    zc* cb;
+    zc* cr;
+    double* resid;
+    int* iters;
+    int* upd;
+    unsigned char* done;
+    unsigned char* stat;
+    unsigned char* updf;
+    double* red;
+    int* ctl;   // [0] nupd, [1] ndone, [2] new seed
+};
+
+__host__ __device__ inline size_t lds_bytes(int K, int NT) {
+    size_t b = 5 * sizeof(zc) * (size_t)K + sizeof(double) * (size_t)K + 2 * sizeof(int) * (size_t)K;
+    b += 3 * (size_t)K;
+    b = (b + 15) & ~(size_t)15;
+    b += sizeof(double) * (NT / 64) * 4 + 4 * sizeof(int);
+    return b;
+}
+
+__device__ inline Lds lds_carve(unsigned char* base, int K, int NT) {
+    Lds L;
+    unsigned char* q = base;
+    L.pi = (zc*)q; q += sizeof(zc) * K;
+    L.piold = (zc*)q; q += sizeof(zc) * K;
+    L.ca = (zc*)q; q += sizeof(zc) * K;
+    L.cb = (zc*)q; q += sizeof(zc) * K;
+    L.cr = (zc*)q; q += sizeof(zc) * K;
+    L.resid = (double*)q; q += sizeof(double) * K;
+    L.iters = (int*)q; q += sizeof(int) * K;
+    L.upd = (int*)q; q += sizeof(int) * K;
+    L.done = q; q += K;
+    L.stat = q; q += K;
+    L.updf = q; q += K;
+    q = base + (((size_t)(q - base) + 15) & ~(size_t)15);
+    L.red = (double*)q; q += sizeof(double) * (NT / 64) * 4;
+    L.ctl = (int*)q;
+    return L;
+}
+
+// q = (z S - H) p over this thread's rows; returns the partial p^T q.
+template <int BD, int NT, class TV, class TB, bool SID>
+__device__ __forceinline__ zc op_apply(const KParams& P, const Sys& sy, zc z, const v2<TV>* __restrict__ p,
+                                       v2<TV>* __restrict__ q) {
+    const TB* __restrict__ H = (const TB*)P.Hv;
+    const TB* __restrict__ S = (const TB*)P.Sv;
+    zc mu = zmk(0.0, 0.0);
+    for (int i = threadIdx.x; i < sy.M; i += NT) {
+        const int a = i / BD, r = i - a * BD;
+        const int64_t e0 = sy.rowptr[a], e1 = sy.rowptr[a + 1];
+        TV hr = 0, hi = 0, sr = 0, si = 0;
+        for (int64_t e = e0; e < e1; ++e) {
+            const int64_t b = sy.ecol[e];
+            const int64_t g = sy.egid[e];
+            const TB* hb = H + (g * BD + r) * BD;
+            const v2<TV>* pb = p + b * BD;
+            if constexpr (SID) {
+#pragma unroll
+                for (int c = 0; c < BD; ++c) {
+                    const v2<TV> pv = pb[c];
+                    const TV h = (TV)bval(hb, c);
+                    hr += h * pv.x;
+                    hi += h * pv.y;
+                }
+            } else {
+                const TB* sb = S + (g * BD + r) * BD;
+#pragma unroll
+                for (int c = 0; c < BD; ++c) {
+                    const v2<TV> pv = pb[c];
+                    const TV h = (TV)bval(hb, c);
+                    const TV s = (TV)bval(sb, c);
+                    hr += h * pv.x;
+                    hi += h * pv.y;
+                    sr += s * pv.x;
+                    si += s * pv.y;
+                }
+            }
+        }
+        const zc pi_ = ld<TV>(p, i);
+        const zc sp = SID ? pi_ : zmk((double)sr, (double)si);
+        zc qv = zsub(zmul(z, sp), zmk((double)hr, (double)hi));
+        st<TV>(q, i, qv);
+        qv = ld<TV>(q, i);   // the stored (possibly rounded) value enters p^T q
+        mu = zadd(mu, zmul(pi_, qv));
+    }
+    return mu;
+}
+
+// w = S d over this thread's rows; returns the partial Re(d^H w).
+template <int BD, int NT, class TV, class TB>
+__device__ __forceinline__ double spmv_S(const KParams& P, const Sys& sy, const v2<TV>* __restrict__ d,
+                                         v2<TV>* __restrict__ w) {
+    const TB* __restrict__ S = (const TB*)P.Sv;
+    double part = 0.0;
+    for (int i = threadIdx.x; i < sy.M; i += NT) {
+        const int a = i / BD, r = i - a * BD;
+        const int64_t e0 = sy.rowptr[a], e1 = sy.rowptr[a + 1];
+        TV sr = 0, si = 0;
+        for (int64_t e = e0; e < e1; ++e) {
+            const int64_t b = sy.ecol[e];
+            const int64_t g = sy.egid[e];
+            const TB* sb = S + (g * BD + r) * BD;
+            const v2<TV>* db = d + b * BD;
+#pragma unroll
+            for (int c = 0; c < BD; ++c) {
+                const v2<TV> dv = db[c];
+                const TV s = (TV)bval(sb, c);
+                sr += s * dv.x;
+                si += s * dv.y;
+            }
+        }
+        const zc wv = zmk((double)sr, (double)si);
+        st<TV>(w, i, wv);
+        const zc ws = ld<TV>(w, i);
+        const zc dv = ld<TV>(d, i);
+        part += dv.re * ws.re + dv.im * ws.im;
+    }
+    return part;
+}
+
+// Solve S r = rho (Hermitian CG from r = 0) to ||res|| <= tol ||rho||.
+// nr2 = ||rho||^2 (already reduced).  Returns the iteration count.
+template <int BD, int NT, class TV, class TB>
+__device__ int inner_cg(const KParams& P, const Sys& sy, const v2<TV>* rho, v2<TV>* r, v2<TV>* res,
+                        v2<TV>* d, v2<TV>* w, double nr2, double tol, int maxit, double* red) {
+    for (int i = threadIdx.x; i < sy.M; i += NT) {
+        const zc v = ld<TV>(rho, i);
+        st<TV>(r, i, zmk(0.0, 0.0));
+        st<TV>(res, i, v);
+        st<TV>(d, i, v);
+    }
+    if (nr2 == 0.0) return 0;
+    __syncthreads();
+    const double stop = tol * sqrt(nr2);
+    double rr = nr2;
+    int it = 0;
+    while (it < maxit && !(sqrt(rr) <= stop)) {
+        double dw[1] = {spmv_S<BD, NT, TV, TB>(P, sy, d, w)};
+        block_sum<NT, 1>(dw, red);
+        const double a = rr / dw[0];
+        double rn[1] = {0.0};
+        for (int i = threadIdx.x; i < sy.M; i += NT) {
+            const zc dv = ld<TV>(d, i), wv = ld<TV>(w, i);
+            zc rv = ld<TV>(r, i), sv = ld<TV>(res, i);
+            rv = zmk(rv.re + a * dv.re, rv.im + a * dv.im);
+            sv = zmk(sv.re - a * wv.re, sv.im - a * wv.im);
+            st<TV>(r, i, rv);
+            st<TV>(res, i, sv);
+            const zc s2 = ld<TV>(res, i);
+            rn[0] += s2.re * s2.re + s2.im * s2.im;
+        }
+        block_sum<NT, 1>(rn, red);
+        const double bt = rn[0] / rr;
+        for (int i = threadIdx.x; i < sy.M; i += NT) {
+            const zc sv = ld<TV>(res, i), dv = ld<TV>(d, i);
+            st<TV>(d, i, zmk(sv.re + bt * dv.re, sv.im + bt * dv.im));
+        }
+        __syncthreads();
+        rr = rn[0];
+        ++it;
+    }
+    return it;
+}
+
+// x_k += ca_k p_k;  p_k = cr_k r + cb_k p_k  for the listed shifts.
+// Work items are (256-element chunk, group of 8 shifts), one per wave, so
+// each wave streams contiguous 1 KB segments and keeps its r chunk in
+// registers across the shift group.
+template <int NT, class TV>
+__device__ __forceinline__ void shift_update(v2<TV>* __restrict__ x, v2<TV>* __restrict__ p,
+                                             const v2<TV>* __restrict__ r, int M, int64_t Mp,
+                                             const Lds& L, int nupd) {
+    constexpr int NW = NT / 64, KG = 8;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nch = (M + 255) / 256;
+    const int nkg = (nupd + KG - 1) / KG;
+    for (int item = w; item < nch * nkg; item += NW) {
+        const int kg = item / nch, ch = item - kg * nch;
+        const int base = ch * 256 + lane;
+        zc rv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = base + u * 64;
+            rv[u] = i < M ? ld<TV>(r, i) : zmk(0.0, 0.0);
+        }
+        const int k1 = min(nupd, (kg + 1) * KG);
+        for (int kk = kg * KG; kk < k1; ++kk) {
+            const int k = L.upd[kk];
+            const zc A = L.ca[k], B = L.cb[k], C = L.cr[k];
+            v2<TV>* xk = x + (int64_t)k * Mp;
+            v2<TV>* pk = p + (int64_t)k * Mp;
+            zc xv[4], pv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = base + u * 64;
+                if (i < M) {
+                    xv[u] = ld<TV>(xk, i);
+                    pv[u] = ld<TV>(pk, i);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = base + u * 64;
+                if (i < M) {
+                    st<TV>(xk, i, zadd(xv[u], zmul(A, pv[u])));
+                    st<TV>(pk, i, zadd(zmul(C, rv[u]), zmul(B, pv[u])));
+                }
+            }
+        }
+    }
+}
+
+// Set x_k = 0, p_k = r for every shift.
+template <int NT, class TV>
+__device__ void shift_init(v2<TV>* x, v2<TV>* p, const v2<TV>* r, int M, int64_t Mp, int K) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nch = (M + 63) / 64;
+    for (int item = w; item < nch * K; item += NW) {
+        const int k = item / nch, ch = item - k * nch;
+        const int i = ch * 64 + lane;
+        if (i < M) {
+            st<TV>(x + (int64_t)k * Mp, i, zmk(0.0, 0.0));
+            st<TV>(p + (int64_t)k * Mp, i, ld<TV>(r, i));
+        }
+    }
+}
+
+// Compact the shifts with updf[k] set into L.upd (wave 0), count done shifts.
+template <int NT>
+__device__ __forceinline__ void compact(const Lds& L, int K) {
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        int cnt = 0, nd = 0;
+        for (int base = 0; base < K; base += 64) {
+            const int k = base + lane;
+            const bool f = k < K && L.updf[k];
+            const bool dn = k < K && L.done[k];
+            const uint64_t m = __ballot(f);
+            const uint64_t md = __ballot(dn);
+            const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+            if (f) L.upd[cnt + below] = k;
+            cnt += __popcll(m);
+            nd += __popcll(md);
+        }
+        if (lane == 0) {
+            L.ctl[0] = cnt;
+            L.ctl[1] = nd;
+        }
+    }
+}
+
+// Unconverged shift with the smallest |pi| (largest residual estimate), ties
+// to the lowest index; written to L.ctl[2] by wave 0.
+__device__ __forceinline__ void pick_seed(const Lds& L, int K) {
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        double best = INFINITY;
+        int bk = 0x7fffffff;
+        for (int k = lane; k < K; k += 64) {
+            if (!L.done[k]) {
+                const double m = zabs(L.pi[k]);
+                if (m < best) { best = m; bk = k; }
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ob = __shfl_xor(best, off, 64);
+            const int ok = __shfl_xor(bk, off, 64);
+            if (ob < best || (ob == best && ok < bk)) { best = ob; bk = ok; }
+        }
+        if (lane == 0) L.ctl[2] = bk;
+    }
+}
+
+template <int BD, int NT, class TV, class TB, bool SID>
+__device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
+    const int tid = threadIdx.x;
+    const int K = P.K;
+    const RhsInfo ri = P.rhs[rj];
+    const SysInfo si = P.sys[ri.sys];
+    Sys sy;
+    sy.rowptr = P.rowptr_l + si.row_base;
+    sy.ecol = P.ecol + si.ent_base;
+    sy.egid = P.egid + si.ent_base;
+    sy.nrows = si.nrows;
+    sy.M = si.nrows * BD;
+    const int M = sy.M;
+    const int64_t Mp = P.Mp;
+
+    v2<TV>* x = (v2<TV>*)ws;
+    v2<TV>* p = x + (int64_t)K * Mp;
+    v2<TV>* rho = p + (int64_t)K * Mp;
+    v2<TV>* rbuf = rho + Mp;
+    v2<TV>* q = rbuf + Mp;
+    v2<TV>* res = q + Mp;
+    v2<TV>* d = res + Mp;
+    v2<TV>* w = d + Mp;
+    v2<TV>* r = SID ? rho : rbuf;    // S = I: r = S^{-1} rho = rho
+
+    const int maxiter = P.maxiter > 0 ? P.maxiter : max(1000, 4 * M);
+    const double itol = sizeof(TV) == 8 ? P.inner_tol : P.inner_tol_lo;
+    const double nu0 = 1.0;   // ||e_j||
+    int64_t inner_total = 0, sum_upd = 0, nswitch = 0;
+
+    // ---- init: rho = e_j, r = S^{-1} rho, gamma = rho^T r, x_k = 0, p_k = r
+    for (int i = tid; i < M; i += NT) st<TV>(rho, i, zmk(i == ri.b_local ? 1.0 : 0.0, 0.0));
+    __syncthreads();
+    if constexpr (!SID) inner_total += inner_cg<BD, NT, TV, TB>(P, sy, rho, r, res, d, w, 1.0, itol,
+                                                                P.inner_maxiter, L.red);
+    double gp[2] = {0.0, 0.0};
+    for (int i = tid; i < M; i += NT) {
+        const zc a = ld<TV>(rho, i), b = ld<TV>(r, i);
+        const zc t = zmul(a, b);
+        gp[0] += t.re;
+        gp[1] += t.im;
+    }
+    block_sum<NT, 2>(gp, L.red);
+    zc gamma = zmk(gp[0], gp[1]);
+    for (int k = tid; k < K; k += NT) {
+        L.pi[k] = zmk(1.0, 0.0);
+        L.piold[k] = zmk(1.0, 0.0);
+        L.done[k] = 0;
+        L.stat[k] = ST_MAXITER;
+        L.iters[k] = -1;
+        L.resid[k] = INFINITY;
+    }
+    shift_init<NT, TV>(x, p, r, M, Mp, K);
+    __syncthreads();
+
+    int s = P.seed0;
+    zc alpha_prev = zmk(1.0, 0.0), beta_prev = zmk(0.0, 0.0);
+    int n_outer = 0;
+
+    for (int n = 0; n < maxiter; ++n) {
+        n_outer = n + 1;
+        const zc zs = zmk(P.z[2 * s], P.z[2 * s + 1]);
+        // ---- q = (z_s S - H) p_s, mu = p_s^T q
+        const zc mup = op_apply<BD, NT, TV, TB, SID>(P, sy, zs, p + (int64_t)s * Mp, q);
+        double mr[2] = {mup.re, mup.im};
+        block_sum<NT, 2>(mr, L.red);
+        const zc mu = zmk(mr[0], mr[1]);
+        if (!zfinite(mu) || zzero(mu)) {
+            const unsigned char code = zfinite(mu) ? ST_BREAKDOWN : ST_NONFINITE;
+            for (int k = tid; k < K; k += NT)
+                if (!L.done[k]) { L.stat[k] = code; L.done[k] = 1; }
+            break;
+        }
+        const zc alpha = zdiv(gamma, mu);
+        // ---- rho -= alpha q;  nu^2 = ||rho||^2
+        double nn[1] = {0.0};
+        for (int i = tid; i < M; i += NT) {
+            const zc a = zsub(ld<TV>(rho, i), zmul(alpha, ld<TV>(q, i)));
+            st<TV>(rho, i, a);
+            const zc b = ld<TV>(rho, i);
+            nn[0] += b.re * b.re + b.im * b.im;
+        }
+        block_sum<NT, 1>(nn, L.red);
+        const double nu = sqrt(nn[0]);
+        // ---- r = S^{-1} rho
+        if constexpr (!SID) inner_total += inner_cg<BD, NT, TV, TB>(P, sy, rho, r, res, d, w, nn[0], itol,
+                                                                    P.inner_maxiter, L.red);
+        // ---- gamma' = rho^T r
+        double gn[2] = {0.0, 0.0};
+        for (int i = tid; i < M; i += NT) {
+            const zc t = zmul(ld<TV>(rho, i), ld<TV>(r, i));
+            gn[0] += t.re;
+            gn[1] += t.im;
+        }
+        block_sum<NT, 2>(gn, L.red);
+        const zc gamma_new = zmk(gn[0], gn[1]);
+        if (!isfinite(nu) || !zfinite(gamma_new)) {
+            for (int k = tid; k < K; k += NT)
+                if (!L.done[k]) { L.stat[k] = ST_NONFINITE; L.done[k] = 1; }
+            break;
+        }
+        const zc beta = zdiv(gamma_new, gamma);
+        gamma = gamma_new;
+
+        // ---- shift scalars (FP64), one thread per shift
+        const zc c3 = zdiv(zmul(beta_prev, alpha), alpha_prev);
+        for (int k = tid; k < K; k += NT) {
+            L.updf[k] = 0;
+            if (L.done[k]) continue;
+            const zc pk = L.pi[k], po = L.piold[k];
+            const zc dz = zmk(P.z[2 * k] - zs.re, P.z[2 * k + 1] - zs.im);
+            const zc f = zadd(zmk(1.0, 0.0), zmul(alpha, dz));
+            const zc pin = zadd(zmul(f, pk), zmul(c3, zsub(pk, po)));
+            if (!zfinite(pin) || zzero(pin)) {
+                L.stat[k] = zfinite(pin) ? ST_BREAKDOWN : ST_NONFINITE;
+                L.done[k] = 1;
+                continue;
+            }
+            const zc ratio = zdiv(pk, pin);
+            L.ca[k] = zmul(ratio, alpha);
+            L.cb[k] = zmul(zmul(ratio, ratio), beta);
+            L.cr[k] = zdiv(zmk(1.0, 0.0), pin);
+            L.piold[k] = pk;
+            L.pi[k] = pin;
+            const double est = nu / zabs(pin);
+            L.resid[k] = est / nu0;
+            L.updf[k] = 1;
+            if (est < P.tol * nu0) {
+                L.done[k] = 1;
+                L.stat[k] = ST_CONVERGED;
+                L.iters[k] = n + 1;
+            }
+        }
+        __syncthreads();
+        compact<NT>(L, K);
+        __syncthreads();
+        const int nupd = L.ctl[0];
+        const int ndone = L.ctl[1];
+        sum_upd += nupd;
+        // ---- x_k += alpha_k p_k;  p_k = r/pi_k + beta_k p_k
+        shift_update<NT, TV>(x, p, r, M, Mp, L, nupd);
+        __syncthreads();
+        if (zzero(gamma) && nu > 0.0 && ndone < K) {
+            for (int k = tid; k < K; k += NT)
+                if (!L.done[k]) { L.stat[k] = ST_BREAKDOWN; L.done[k] = 1; }
+            break;
+        }
+        if (ndone == K) break;
+        zc alpha_n = alpha, beta_n = beta;
+        if (L.done[s]) {
+            // ---- seed switch
+            pick_seed(L, K);
+            __syncthreads();
+            const int s2 = L.ctl[2];
+            const zc cn = L.pi[s2], co = L.piold[s2];
+            __syncthreads();
+            const zc ratio = zdiv(co, cn);
+            alpha_n = zmul(ratio, alpha);
+            beta_n = zmul(zmul(ratio, ratio), beta);
+            const zc icn = zdiv(zmk(1.0, 0.0), cn);
+            for (int i = tid; i < M; i += NT) {
+                st<TV>(rho, i, zdiv(ld<TV>(rho, i), cn));
+                if constexpr (!SID) st<TV>(r, i, zdiv(ld<TV>(r, i), cn));
+            }
+            (void)icn;
+            gamma = zdiv(gamma, zmul(cn, cn));
+            for (int k = tid; k < K; k += NT) {
+                if (!L.done[k]) {
+                    L.pi[k] = zdiv(L.pi[k], cn);
+                    L.piold[k] = zdiv(L.piold[k], co);
+                }
+            }
+            s = s2;
+            ++nswitch;
+            __syncthreads();
+        }
+        alpha_prev = alpha_n;
+        beta_prev = beta_n;
+    }
+    __syncthreads();
+
+    // ---- outputs: G rows (or all of x), iteration counts, codes, estimates
+    const int nout = ri.full_x ? M : ri.nout;
+    const int64_t obase = P.out_off[rj] * (int64_t)K;
+    const int32_t* ol = P.out_local + ri.out_base;
+    for (int64_t idx = tid; idx < (int64_t)K * nout; idx += NT) {
+        const int k = (int)(idx / nout), o = (int)(idx - (int64_t)k * nout);
+        const int row = ri.full_x ? o : ol[o];
+        const zc v = ld<TV>(x + (int64_t)k * Mp, row);
+        P.out[2 * (obase + idx)] = v.re;
+        P.out[2 * (obase + idx) + 1] = v.im;
+    }
+    for (int k = tid; k < K; k += NT) {
+        const int64_t o = (int64_t)rj * K + k;
+        if (P.iters) P.iters[o] = L.iters[k];
+        if (P.status) P.status[o] = (int8_t)L.stat[k];
+        if (P.resid) P.resid[o] = L.resid[k];
+    }
+    if (tid == 0 && P.stats) {
+        int64_t* st_ = P.stats + (int64_t)rj * NSTAT;
+        st_[0] = n_outer;
+        st_[1] = sum_upd;
+        st_[2] = inner_total;
+        st_[3] = nswitch;
+        st_[4] = M;
+        st_[5] = sy.rowptr[sy.nrows] - sy.rowptr[0];
+        st_[6] = 0;
+        st_[7] = 0;
+    }
+    __syncthreads();
+}
+
+template <int BD, int NT, class TV, class TB, bool SID>
+__global__ __launch_bounds__(NT) void k_scocg(KParams P) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_job;
+    const Lds L = lds_carve(smem, P.K, NT);
+    char* ws = P.ws + (int64_t)blockIdx.x * P.slot_bytes;
+    for (;;) {
+        if (threadIdx.x == 0) s_job = atomicAdd(P.queue, 1);
+        __syncthreads();
+        const int job = s_job;
+        __syncthreads();
+        if (job >= P.nrhs) break;
+        solve_one<BD, NT, TV, TB, SID>(P, P.order[job], ws, L);
+    }
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+}  // namespace scocg
+
+// ---------------------------------------------------------------------------
+// launch table
+// ---------------------------------------------------------------------------
+#include "scocg_launch.hpp"
+
+namespace scocg {
+
+template <int BD, int NT, class TV, class TB, bool SID>
+static hipError_t launch_one(const KParams& P, int slots, hipStream_t st) {
+    const size_t lds = lds_bytes(P.K, NT);
+    hipLaunchKernelGGL((k_scocg<BD, NT, TV, TB, SID>), dim3(slots), dim3(NT), lds, st, P);
+    return hipGetLastError();
+}
+
+template <int BD, int NT>
+static hipError_t launch_prec(const KParams& P, int prec, bool sid, int slots, hipStream_t st) {
+    if (prec == 0) return sid ? launch_one<BD, NT, double, double, true>(P, slots, st)
+                              : launch_one<BD, NT, double, double, false>(P, slots, st);
+    if (prec == 1) return sid ? launch_one<BD, NT, float, float, true>(P, slots, st)
+                              : launch_one<BD, NT, float, float, false>(P, slots, st);
+    return sid ? launch_one<BD, NT, float, bf16_t, true>(P, slots, st)
+               : launch_one<BD, NT, float, bf16_t, false>(P, slots, st);
+}
+
+template <int BD>
+static hipError_t launch_nt(const KParams& P, int prec, bool sid, int nt, int slots, hipStream_t st) {
+    if (nt == 256) return launch_prec<BD, 256>(P, prec, sid, slots, st);
+    if (nt == 1024) return launch_prec<BD, 1024>(P, prec, sid, slots, st);
+    return launch_prec<BD, 512>(P, prec, sid, slots, st);
+}
+
+bool supported_bdim(int bd) { return bd == 1 || bd == 4 || bd == 9; }
+
+size_t solver_lds_bytes(int K, int nt) { return lds_bytes(K, nt); }
+
+hipError_t launch_solver(const KParams& P, int bd, int prec, bool sid, int nt, int slots, hipStream_t st) {
+    switch (bd) {
+        case 1: return launch_nt<1>(P, prec, sid, nt, slots, st);
+        case 4: return launch_nt<4>(P, prec, sid, nt, slots, st);
+        case 9: return launch_nt<9>(P, prec, sid, nt, slots, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace scocg

@@ -1,0 +1,66 @@
+"""Shared comparison rules for GPU-vs-oracle parity tests.
+
+Rule: per (RHS, shift), ||x_gpu - x_oracle|| / ||x_oracle|| <= rtol (1e-8
+for FP64), the statuses agree, and the iteration counts agree within
+max(max_shift, iter_frac * n).  Counts move because the two implementations
+sum in different orders: in finite precision the convergence delay of a
+Lanczos-type recurrence depends on the rounding history (the tests also
+check that the trajectories agree closely at fixed iteration counts, before
+that amplification).  If the relative difference exceeds rtol while the
+counts differ, both results must lie within the a-priori bound
+||x - x*|| <= ||A^-1||_2 * slack * tol * ||b|| of the dense solution x*,
+with ||A^-1||_2 computed exactly.  Anything else fails.  Every mismatch is
+collected before asserting so a failure reports the whole picture.
+
+Two CPU runs of the oracle that differ only in the matrix-vector summation
+order (sparse vs dense product) already differ by up to ~5% in iteration
+counts and ~3e-10 in the converged x on these workloads; the 8% allowance
+and the 1e-8 bar sit above that natural spread.
+"""
+import numpy as np
+
+from oracle import dense_solve
+
+
+def inv_norm(Hc, Sc, z):
+    Hd = Hc.toarray()
+    Sd = np.eye(Hd.shape[0]) if Sc is None else Sc.toarray()
+    return 1.0 / np.linalg.svd(z * Sd - Hd, compute_uv=False)[-1]
+
+
+def compare_rhs(xg, itg, stg, res, Hc, Sc, shifts, b, tol, rtol=1e-8, slack=2.0, report=None,
+                max_shift=3, iter_frac=0.08, tag=""):
+    """xg: [K, M] GPU x; res: oracle ScocgResult with x [M, K].  Returns worst rel err."""
+    K = shifts.size
+    worst = 0.0
+    errs = []
+    for k in range(K):
+        xo = res.x[:, k]
+        if stg[k] != res.status[k]:
+            errs.append(f"{tag} shift {k}: status gpu {stg[k]} oracle {res.status[k]}")
+            continue
+        rel = np.linalg.norm(xg[k] - xo) / np.linalg.norm(xo)
+        worst = max(worst, rel)
+        d = abs(int(itg[k]) - int(res.iters[k]))
+        if d > max(max_shift, iter_frac * max(int(res.iters[k]), 1)):
+            errs.append(f"{tag} shift {k}: iterations gpu {itg[k]} oracle {res.iters[k]}")
+            continue
+        if rel <= rtol:
+            if d and report is not None:
+                report.append((tag, k, int(itg[k]), int(res.iters[k]), float(rel)))
+            continue
+        if d == 0:
+            errs.append(f"{tag} shift {k}: rel err {rel:.3e} > {rtol:.1e} (iters {itg[k]})")
+            continue
+        xs = dense_solve(Hc, Sc, shifts[k], b)
+        bound = inv_norm(Hc, Sc, shifts[k]) * slack * tol * np.linalg.norm(b)
+        eg, eo = np.linalg.norm(xg[k] - xs), np.linalg.norm(xo - xs)
+        if not (eg <= bound and eo <= bound):
+            errs.append(f"{tag} shift {k}: off-by-{d} and outside bound (gpu {eg:.2e} oracle {eo:.2e} "
+                        f"bound {bound:.2e})")
+        if report is not None:
+            report.append((tag, k, int(itg[k]), int(res.iters[k]), float(rel)))
+    if errs:
+        print("\n".join(errs), flush=True)
+    assert not errs, f"{len(errs)} parity failures, first: {errs[0]}"
+    return worst
