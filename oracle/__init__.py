@@ -8,6 +8,6 @@ the seeded input generator in ``synth``.
 """
 from .scocg import (  # noqa: F401
     CONVERGED, MAXITER, BREAKDOWN, NONFINITE, ScocgResult, initial_seed,
-    inner_cg, scocg, local_system, solve_rhs, solve_problem,
+    inner_cg, scocg, scocg_projected, local_system, solve_rhs, solve_problem,
 )
 from .dense import dense_solve, green_eig, true_residual  # noqa: F401

@@ -236,6 +236,128 @@ def scocg(H, S, z, b, tol: float, maxiter: Optional[int] = None, inner_tol: floa
     return ScocgResult(x, iters, status, resid, n_outer, inner_total, seeds)
 
 
+def scocg_projected(H, S, z, b, rows, tol: float, maxiter: Optional[int] = None,
+                    inner_tol: float = 1e-13, inner_maxiter: int = 1000, seed: Optional[int] = None,
+                    s_solve: Optional[Callable] = None) -> ScocgResult:
+    """Shifted COCG tracking only the rows ``rows`` of every x_k (projected G).
+
+    The seed runs the three-term (Lanczos) form of COCG, which needs no
+    search direction: with r = S^{-1} rho and q = (z_s S - H) r,
+        mu_n  = r_n^T q_n - beta_{n-1} gamma_n / alpha_{n-1},  alpha_n = gamma_n / mu_n,
+        c_n   = alpha_n beta_{n-1} / alpha_{n-1},
+        rho_{n+1} = (1 + c_n) rho_n - alpha_n q_n - c_n rho_{n-1},
+    obtained from the two-term form by eliminating p_n with
+    (z_s S - H) p_{n-1} = (rho_{n-1} - rho_n) / alpha_{n-1} and the
+    orthogonality of successive residuals.  Every shift (the seed included,
+    with pi = 1) keeps x_k and p_k on ``rows`` only, updated with the same
+    shifted coefficients as in ``scocg``; they read r on ``rows`` only.  A seed
+    switch rescales the two latest residuals by the new seed's pi at the same
+    steps, so no full vector of any other shift is ever needed.
+
+    Returns a ScocgResult whose x is [len(rows), K].
+    """
+    z = np.asarray(z, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    rows = np.asarray(rows, dtype=np.int64)
+    M, K = b.shape[0], z.shape[0]
+    if maxiter is None:
+        maxiter = max(1000, 4 * M)
+    inner_total = 0
+
+    def apply_sinv(v):
+        nonlocal inner_total
+        if S is None:
+            return v.copy()
+        if s_solve is not None:
+            return s_solve(v)
+        out, it = inner_cg(S, v, inner_tol, inner_maxiter)
+        inner_total += it
+        return out
+
+    nu0 = np.linalg.norm(b)
+    xI = np.zeros((rows.size, K), dtype=np.complex128)
+    iters = np.full(K, -1, dtype=np.int64)
+    status = np.full(K, MAXITER, dtype=np.int8)
+    resid = np.full(K, np.inf)
+    rho = b.copy()
+    rho_old = np.zeros_like(rho)
+    r = apply_sinv(rho)
+    r_old = np.zeros_like(r)
+    gamma = rho @ r
+    pI = np.repeat(r[rows][:, None], K, axis=1)
+    pi = np.ones(K, dtype=np.complex128)
+    pi_old = np.ones(K, dtype=np.complex128)
+    done = np.zeros(K, dtype=bool)
+    s = initial_seed(z) if seed is None else int(seed)
+    seeds = [(0, s)]
+    alpha_prev, beta_prev = 1.0 + 0j, 0.0 + 0j
+    n_outer = 0
+    for n in range(maxiter):
+        n_outer = n + 1
+        q = z[s] * (r if S is None else S @ r) - H @ r
+        mu = r @ q - beta_prev * gamma / alpha_prev
+        if not np.isfinite(mu) or mu == 0:
+            status[~done] = NONFINITE if not np.isfinite(mu) else BREAKDOWN
+            done[:] = True
+            break
+        alpha = gamma / mu
+        c = alpha * beta_prev / alpha_prev
+        rho_new = (1.0 + c) * rho - alpha * q - c * rho_old
+        rho_old, rho = rho, rho_new
+        r_new = apply_sinv(rho)
+        r_old, r = r, r_new
+        gamma_new = rho @ r
+        nu = np.linalg.norm(rho)
+        if not np.isfinite(nu) or not np.isfinite(gamma_new):
+            status[~done] = NONFINITE
+            done[:] = True
+            break
+        beta = gamma_new / gamma
+        gamma = gamma_new
+        act = np.flatnonzero(~done)
+        pin = (1.0 + alpha * (z[act] - z[s])) * pi[act] + (beta_prev * alpha / alpha_prev) * (pi[act] - pi_old[act])
+        bad = ~np.isfinite(pin) | (pin == 0)
+        if np.any(bad):
+            kb = act[bad]
+            status[kb] = np.where(np.isfinite(pin[bad]), BREAKDOWN, NONFINITE)
+            done[kb] = True
+            act, pin = act[~bad], pin[~bad]
+        ratio = pi[act] / pin
+        ak = ratio * alpha
+        bk = ratio * ratio * beta
+        xI[:, act] += ak[None, :] * pI[:, act]
+        pI[:, act] = r[rows][:, None] / pin[None, :] + bk[None, :] * pI[:, act]
+        pi_old[act] = pi[act]
+        pi[act] = pin
+        est = nu / np.abs(pin)
+        resid[act] = est / nu0
+        newly = act[est < tol * nu0]
+        done[newly] = True
+        status[newly] = CONVERGED
+        iters[newly] = n + 1
+        if gamma == 0 and nu > 0 and not np.all(done):
+            status[~done] = BREAKDOWN
+            done[:] = True
+            break
+        if np.all(done):
+            break
+        if done[s]:
+            cand = np.flatnonzero(~done)
+            s_new = int(cand[np.argmin(np.abs(pi[cand]))])
+            cn, co = pi[s_new], pi_old[s_new]
+            alpha = (co / cn) * alpha
+            beta = (co / cn) ** 2 * beta
+            rho, rho_old = rho / cn, rho_old / co
+            r, r_old = r / cn, r_old / co
+            gamma = gamma / (cn * cn)
+            pi[cand] = pi[cand] / cn
+            pi_old[cand] = pi_old[cand] / co
+            s = s_new
+            seeds.append((n + 1, s))
+        alpha_prev, beta_prev = alpha, beta
+    return ScocgResult(xI, iters, status, resid, n_outer, inner_total, seeds)
+
+
 # ----------------------------------------------------------------------------
 # problems (global or cluster-restricted) — layout only
 # ----------------------------------------------------------------------------
@@ -269,14 +391,20 @@ def local_system(prob, j: int, Hcsr=None, Scsr=None):
     return Hc, Sc, loc, orb
 
 
-def solve_rhs(prob, j: int, tol: Optional[float] = None, Hcsr=None, Scsr=None, full_x=False, **kw):
-    """Solve RHS number j for all shifts; returns (G [K, nout], result, orbitals)."""
+def solve_rhs(prob, j: int, tol: Optional[float] = None, Hcsr=None, Scsr=None, full_x=False,
+              projected=False, **kw):
+    """Solve RHS number j for all shifts; returns (G [K, nout], result, orbitals).
+
+    ``projected`` uses the three-term, rows-only form (``scocg_projected``)."""
     Hc, Sc, loc, orb = local_system(prob, j, Hcsr, Scsr)
     b = np.zeros(orb.size, dtype=np.complex128)
     b[loc] = 1.0
-    res = scocg(Hc, Sc, prob.shifts, b, prob.tol if tol is None else tol, **kw)
     outs = prob.outs(j)
     pos = np.searchsorted(orb, outs)
+    if projected:
+        res = scocg_projected(Hc, Sc, prob.shifts, b, pos, prob.tol if tol is None else tol, **kw)
+        return res.x.T.copy(), res, orb
+    res = scocg(Hc, Sc, prob.shifts, b, prob.tol if tol is None else tol, **kw)
     G = res.x[pos, :].T.copy()
     if not full_x:
         res.x = None

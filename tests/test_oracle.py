@@ -347,3 +347,55 @@ def test_rounding_amplification_between_cpu_variants(cfg0):
     fb = scocg(D, None, p.shifts, b, p.tol)
     rel = np.linalg.norm(fa.x - fb.x, axis=0) / np.linalg.norm(fa.x, axis=0)
     assert rel.max() < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# projected (rows-only, three-term) form
+# ---------------------------------------------------------------------------
+from oracle import scocg_projected  # noqa: E402
+
+
+@pytest.mark.parametrize("generalized", [False, True])
+def test_projected_vs_dense_lu_and_two_term(cfg0, gen_small, generalized):
+    if generalized:
+        p, H, S = gen_small
+    else:
+        (p, H), S = cfg0, None
+    for j in range(min(3, p.nrhs)):
+        b = _unit(p.M, int(p.rhs[j]))
+        rows = p.outs(j)
+        pr = scocg_projected(H, S, p.shifts, b, rows, p.tol)
+        full = scocg(H, S, p.shifts, b, p.tol)
+        assert np.all(pr.status == CONVERGED) and pr.x.shape == (rows.size, p.nshift)
+        for k, z in enumerate(p.shifts):
+            xs = dense_solve(H, S, z, b)
+            bound = _inv_norm_bound(H, S, z) * 2 * p.tol
+            assert np.linalg.norm(pr.x[:, k] - xs[rows]) <= bound
+            assert np.linalg.norm(pr.x[:, k] - full.x[rows, k]) <= 2 * bound
+
+
+def test_projected_forced_seed_switch(cfg0):
+    p, H = cfg0
+    b = _unit(p.M, int(p.rhs[1]))
+    rows = p.outs(1)
+    pr = scocg_projected(H, None, p.shifts, b, rows, p.tol, seed=0)
+    assert len(pr.seeds) > 1
+    for k, z in enumerate(p.shifts):
+        xs = dense_solve(H, None, z, b)
+        assert np.linalg.norm(pr.x[:, k] - xs[rows]) <= _inv_norm_bound(H, None, z) * 2 * p.tol
+
+
+def test_projected_diagonal_and_2x2():
+    h = np.array([0.3, -1.2, 2.5, 0.7])
+    H = sp.diags(h).tocsr()
+    z = np.array([-1.0 + 0.1j, 0.5 + 0.1j, 2.0 + 0.2j])
+    res = scocg_projected(H, None, z, _unit(4, 2), [2, 0], tol=1e-12)
+    assert res.n_outer == 1
+    assert np.allclose(res.x[0], 1.0 / (z - h[2]), rtol=1e-15) and np.all(res.x[1] == 0)
+    h11, h22, h12 = 0.4, -0.9, 0.35
+    H2 = sp.csr_matrix(np.array([[h11, h12], [h12, h22]]))
+    z2 = np.array([-2.0 + 0.05j, 0.1 + 0.05j, 1.3 + 0.3j])
+    r2 = scocg_projected(H2, None, z2, _unit(2, 0), [0, 1], tol=1e-13)
+    det = (z2 - h11) * (z2 - h22) - h12 ** 2
+    assert np.allclose(r2.x[0], (z2 - h22) / det, rtol=1e-12)
+    assert np.allclose(r2.x[1], h12 / det, rtol=1e-12)
