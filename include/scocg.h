@@ -59,7 +59,8 @@ typedef int32_t scocg_status;
 /* ---- precision of the vectors and stored blocks --------------------------- */
 #define SCOCG_FP64        0  /* complex128 vectors, FP64 blocks */
 #define SCOCG_FP32        1  /* complex64 vectors and SpMV, FP32 blocks; FP64
-                                scalars, FP64 residual replacement, FP64 audit */
+                                scalars; optional FP64 residual replacement;
+                                FP64 audit and single-shift FP64 fallback */
 #define SCOCG_FP32_BF16   2  /* as SCOCG_FP32 but blocks stored as bfloat16 */
 
 /* ---- output modes --------------------------------------------------------- */
@@ -124,7 +125,11 @@ typedef struct {
     double  tol;            /* converge when ||rho|| / |pi_k| < tol * ||b|| (> 0) */
     int32_t maxiter;        /* outer iterations; 0 = max(1000, 4*M_j) */
     int32_t precision;      /* SCOCG_FP64 / SCOCG_FP32 / SCOCG_FP32_BF16 */
-    int32_t replace_every;  /* FP32 forms: FP64 residual replacement period; 0 = off */
+    int32_t replace_every;  /* FP32 forms: FP64 residual replacement of the seed every
+                               this many iterations; 0 = off (default: replacing the
+                               seed residual breaks the collinearity the shifted
+                               recurrences rely on once the FP32 gap is not small
+                               against the residual, so it is opt-in) */
     int32_t inner_maxiter;  /* inner CG iteration cap */
     double  inner_tol;      /* inner CG stop: ||res|| <= inner_tol * ||rho|| (FP64) */
     double  inner_tol_lo;   /* same for the FP32 inner CG */
@@ -132,10 +137,16 @@ typedef struct {
                                nearest the median of Re z, then lowest index */
     int32_t threads;        /* workgroup size 256/512/1024; 0 = default */
     int32_t slots;          /* resident workgroups; 0 = device CUs x occupancy */
-    int32_t audit;          /* FP32 forms: FP64 true-residual audit + FP64 fallback */
+    int32_t audit;          /* 0: off.  1: FP64 true-residual audit of every (RHS, shift);
+                               for the FP32 forms every pair the audit finds above tol
+                               is re-solved from its x by single-shift FP64 COCG.
+                               2: as 1, with the FP64 re-solve for FP64 too.
+                               With the audit on, resid holds the audited residual,
+                               and a re-solved pair is CONVERGED only if its audited
+                               residual is <= tol (MAXITER otherwise). */
 } scocg_options;
 
-/* Defaults: tol 1e-10, maxiter 0, FP64, replace_every 20, inner_maxiter 1000,
+/* Defaults: tol 1e-10, maxiter 0, FP64, replace_every 0, inner_maxiter 1000,
  * inner_tol 1e-13, inner_tol_lo 1e-6, seed_index -1, threads 0, slots 0, audit 1. */
 void scocg_options_default(scocg_options* opt);
 
@@ -187,6 +198,15 @@ void scocg_plan_free(scocg_plan* plan);
  * K * out_offset(r) and are laid out [shift][row].
  */
 int64_t scocg_plan_out_count(const scocg_plan* plan);
+/*
+ * Launch shape of a plan, host int64[SCOCG_NINFO]: [0] resident workgroups,
+ * [1] threads per workgroup, [2] padded rows per workgroup slot, [3] bytes of
+ * one slot, [4] initial seed index, [5] LDS bytes per workgroup,
+ * [6] precision, [7] 1 if every RHS uses the whole system.
+ */
+#define SCOCG_NINFO 8
+scocg_status scocg_plan_info(const scocg_plan* plan, int64_t* info);
+
 /* out_offset(r) for every RHS (host int64[nrhs+1], prefix sums of n_out). */
 scocg_status scocg_plan_out_offsets(const scocg_plan* plan, int64_t* offsets);
 

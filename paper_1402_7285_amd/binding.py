@@ -28,7 +28,7 @@ STAT_NAMES = ("outer", "sum_upd", "inner", "switches", "M", "blocks", "replaceme
 EXPORTS = (
     "scocg_last_error", "scocg_version", "scocg_matrix_from_bsr", "scocg_matrix_from_csr",
     "scocg_matrix_free", "scocg_problem_create", "scocg_problem_free", "scocg_options_default",
-    "scocg_plan_create", "scocg_plan_free", "scocg_plan_out_count", "scocg_plan_out_offsets",
+    "scocg_plan_create", "scocg_plan_free", "scocg_plan_out_count", "scocg_plan_out_offsets", "scocg_plan_info",
     "scocg_plan_run", "scocg_plan_stats", "scocg_solve",
 )
 
@@ -75,6 +75,7 @@ def _declare(lib):
         "scocg_plan_free": (None, [_VP]),
         "scocg_plan_out_count": (i64, [_VP]),
         "scocg_plan_out_offsets": (st, [_VP, _VP]),
+        "scocg_plan_info": (st, [_VP, _VP]),
         "scocg_plan_run": (st, [_VP, _VP, _VP, _VP, _VP, _VP]),
         "scocg_plan_stats": (st, [_VP, _VP]),
         "scocg_solve": (st, [_VP, C.POINTER(scocg_options), i32, _VP, i32, _VP,
@@ -204,6 +205,16 @@ def scocg_plan_out_offsets(h, nrhs) -> np.ndarray:
     return off
 
 
+NINFO = 8
+INFO_NAMES = ("slots", "threads", "Mp", "slot_bytes", "seed0", "lds_bytes", "precision", "global")
+
+
+def scocg_plan_info(h) -> dict:
+    info = np.zeros(NINFO, dtype=np.int64)
+    _check(load().scocg_plan_info(h, _ptr(info)))
+    return dict(zip(INFO_NAMES, (int(v) for v in info)))
+
+
 def scocg_plan_run(h, stream, out, iters=None, status=None, resid=None):
     """Device buffers are torch CUDA tensors; stream a torch.cuda.Stream or None."""
     sp = None if stream is None else C.c_void_p(stream.cuda_stream)
@@ -277,6 +288,8 @@ class Plan:
         self.h = scocg_plan_create(problem.h, self.opt, self.shifts, self.rhs, self.spec)
         self.out_count = scocg_plan_out_count(self.h)
         self.out_offsets = scocg_plan_out_offsets(self.h, self.nrhs)
+        self.info = scocg_plan_info(self.h)
+        self.slots = self.info["slots"]
 
     def alloc_outputs(self, device="cuda"):
         import torch

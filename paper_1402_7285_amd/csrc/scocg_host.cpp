@@ -364,7 +364,7 @@ extern "C" void scocg_options_default(scocg_options* o) {
     o->tol = 1e-10;
     o->maxiter = 0;
     o->precision = SCOCG_FP64;
-    o->replace_every = 20;
+    o->replace_every = 0;
     o->inner_maxiter = 1000;
     o->inner_tol = 1e-13;
     o->inner_tol_lo = 1e-6;
@@ -643,8 +643,7 @@ extern "C" scocg_status scocg_plan_create(scocg_problem* P, const scocg_options*
     pl->out_count = hm.outoff[nrhs] * (int64_t)nshift;
     pl->nt = opt.threads ? opt.threads : 512;
     pl->Mp = std::max<int64_t>(64, (hm.maxM + 63) / 64 * 64);
-    const int64_t vsz = opt.precision == SCOCG_FP64 ? 16 : 8;
-    pl->slot_bytes = ((2 * (int64_t)nshift + 6) * pl->Mp * vsz + 255) / 256 * 256;
+    pl->slot_bytes = scocg::solver_slot_bytes(nshift, pl->Mp, opt.precision);
 
     auto bail = [&](scocg_status e) { scocg_plan_free(pl); return e; };
     int cus = 0;
@@ -699,6 +698,19 @@ extern "C" scocg_status scocg_plan_create(scocg_problem* P, const scocg_options*
 }
 
 extern "C" int64_t scocg_plan_out_count(const scocg_plan* pl) { return pl ? pl->out_count : -1; }
+
+extern "C" scocg_status scocg_plan_info(const scocg_plan* pl, int64_t* info) {
+    if (!pl || !info) return fail(SCOCG_E_ARG, "NULL argument");
+    info[0] = pl->slots;
+    info[1] = pl->nt;
+    info[2] = pl->Mp;
+    info[3] = pl->slot_bytes;
+    info[4] = pl->seed0;
+    info[5] = (int64_t)scocg::solver_lds_bytes(pl->K, pl->nt);
+    info[6] = pl->prec;
+    info[7] = pl->global ? 1 : 0;
+    return SCOCG_OK;
+}
 
 extern "C" scocg_status scocg_plan_out_offsets(const scocg_plan* pl, int64_t* offsets) {
     if (!pl || !offsets) return fail(SCOCG_E_ARG, "NULL argument");

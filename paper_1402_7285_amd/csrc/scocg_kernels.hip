@@ -53,13 +53,14 @@ struct Lds {
     unsigned char* done;
     unsigned char* stat;
     unsigned char* updf;
+    unsigned char* dirty;   // FP32 forms: x_lo holds unflushed updates
     double* red;
-    int* ctl;   // [0] nupd, [1] ndone, [2] new seed
+    int* ctl;   // [0] nupd, [1] ndone, [2] new seed, [3] flush count
 };
 
 __host__ __device__ inline size_t lds_bytes(int K, int NT) {
     size_t b = 5 * sizeof(zc) * (size_t)K + sizeof(double) * (size_t)K + 2 * sizeof(int) * (size_t)K;
-    b += 3 * (size_t)K;
+    b += 4 * (size_t)K;
     b = (b + 15) & ~(size_t)15;
     b += sizeof(double) * (NT / 64) * 4 + 4 * sizeof(int);
     return b;
@@ -79,6 +80,7 @@ __device__ inline Lds lds_carve(unsigned char* base, int K, int NT) {
     L.done = q; q += K;
     L.stat = q; q += K;
     L.updf = q; q += K;
+    L.dirty = q; q += K;
     q = base + (((size_t)(q - base) + 15) & ~(size_t)15);
     L.red = (double*)q; q += sizeof(double) * (NT / 64) * 4;
     L.ctl = (int*)q;
@@ -87,10 +89,8 @@ __device__ inline Lds lds_carve(unsigned char* base, int K, int NT) {
 
 // q = (z S - H) p over this thread's rows; returns the partial p^T q.
 template <int BD, int NT, class TV, class TB, bool SID>
-__device__ __forceinline__ zc op_apply(const KParams& P, const Sys& sy, zc z, const v2<TV>* __restrict__ p,
-                                       v2<TV>* __restrict__ q) {
-    const TB* __restrict__ H = (const TB*)P.Hv;
-    const TB* __restrict__ S = (const TB*)P.Sv;
+__device__ __forceinline__ zc op_apply(const TB* __restrict__ H, const TB* __restrict__ S, const Sys& sy, zc z,
+                                       const v2<TV>* __restrict__ p, v2<TV>* __restrict__ q) {
     zc mu = zmk(0.0, 0.0);
     for (int i = threadIdx.x; i < sy.M; i += NT) {
         const int a = i / BD, r = i - a * BD;
@@ -135,9 +135,8 @@ __device__ __forceinline__ zc op_apply(const KParams& P, const Sys& sy, zc z, co
 
 // w = S d over this thread's rows; returns the partial Re(d^H w).
 template <int BD, int NT, class TV, class TB>
-__device__ __forceinline__ double spmv_S(const KParams& P, const Sys& sy, const v2<TV>* __restrict__ d,
+__device__ __forceinline__ double spmv_S(const TB* __restrict__ S, const Sys& sy, const v2<TV>* __restrict__ d,
                                          v2<TV>* __restrict__ w) {
-    const TB* __restrict__ S = (const TB*)P.Sv;
     double part = 0.0;
     for (int i = threadIdx.x; i < sy.M; i += NT) {
         const int a = i / BD, r = i - a * BD;
@@ -168,7 +167,7 @@ __device__ __forceinline__ double spmv_S(const KParams& P, const Sys& sy, const 
 // Solve S r = rho (Hermitian CG from r = 0) to ||res|| <= tol ||rho||.
 // nr2 = ||rho||^2 (already reduced).  Returns the iteration count.
 template <int BD, int NT, class TV, class TB>
-__device__ int inner_cg(const KParams& P, const Sys& sy, const v2<TV>* rho, v2<TV>* r, v2<TV>* res,
+__device__ int inner_cg(const TB* S, const Sys& sy, const v2<TV>* rho, v2<TV>* r, v2<TV>* res,
                         v2<TV>* d, v2<TV>* w, double nr2, double tol, int maxit, double* red) {
     for (int i = threadIdx.x; i < sy.M; i += NT) {
         const zc v = ld<TV>(rho, i);
@@ -182,7 +181,7 @@ __device__ int inner_cg(const KParams& P, const Sys& sy, const v2<TV>* rho, v2<T
     double rr = nr2;
     int it = 0;
     while (it < maxit && !(sqrt(rr) <= stop)) {
-        double dw[1] = {spmv_S<BD, NT, TV, TB>(P, sy, d, w)};
+        double dw[1] = {spmv_S<BD, NT, TV, TB>(S, sy, d, w)};
         block_sum<NT, 1>(dw, red);
         const double a = rr / dw[0];
         double rn[1] = {0.0};
@@ -257,9 +256,9 @@ __device__ __forceinline__ void shift_update(v2<TV>* __restrict__ x, v2<TV>* __r
     }
 }
 
-// Set x_k = 0, p_k = r for every shift.
+// Set x_k = 0, p_k = r for every shift (and the FP64 accumulator x_hi = 0).
 template <int NT, class TV>
-__device__ void shift_init(v2<TV>* x, v2<TV>* p, const v2<TV>* r, int M, int64_t Mp, int K) {
+__device__ void shift_init(v2<TV>* x, v2<TV>* p, double2* xhi, const v2<TV>* r, int M, int64_t Mp, int K) {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nch = (M + 63) / 64;
@@ -269,31 +268,33 @@ __device__ void shift_init(v2<TV>* x, v2<TV>* p, const v2<TV>* r, int M, int64_t
         if (i < M) {
             st<TV>(x + (int64_t)k * Mp, i, zmk(0.0, 0.0));
             st<TV>(p + (int64_t)k * Mp, i, ld<TV>(r, i));
+            if (xhi) xhi[(int64_t)k * Mp + i] = make_double2(0.0, 0.0);
         }
     }
 }
 
-// Compact the shifts with updf[k] set into L.upd (wave 0), count done shifts.
-template <int NT>
-__device__ __forceinline__ void compact(const Lds& L, int K) {
+// Compact the shifts whose flag is set into out[] (wave 0); the count goes
+// to *cnt_out and, if nd_out is given, the number of done shifts to *nd_out.
+__device__ __forceinline__ void compact_flags(const unsigned char* flag, const unsigned char* done, int K,
+                                              int* out, int* cnt_out, int* nd_out) {
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
         int cnt = 0, nd = 0;
         for (int base = 0; base < K; base += 64) {
             const int k = base + lane;
-            const bool f = k < K && L.updf[k];
-            const bool dn = k < K && L.done[k];
+            const bool f = k < K && flag[k];
+            const bool dn = k < K && done != nullptr && done[k];
             const uint64_t m = __ballot(f);
             const uint64_t md = __ballot(dn);
             const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
-            if (f) L.upd[cnt + below] = k;
+            if (f) out[cnt + below] = k;
             cnt += __popcll(m);
             nd += __popcll(md);
         }
         if (lane == 0) {
-            L.ctl[0] = cnt;
-            L.ctl[1] = nd;
+            *cnt_out = cnt;
+            if (nd_out) *nd_out = nd;
         }
     }
 }
@@ -321,8 +322,115 @@ __device__ __forceinline__ void pick_seed(const Lds& L, int K) {
     }
 }
 
+// x_hi_k += x_lo_k; x_lo_k = 0 for the listed shifts (FP32 forms).
+template <int NT>
+__device__ void flush_lo(float2* xlo, double2* xhi, int M, int64_t Mp, const int* list, int n) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nch = (M + 63) / 64;
+    for (int item = w; item < nch * n; item += NW) {
+        const int kk = item / nch, ch = item - kk * nch;
+        const int i = ch * 64 + lane;
+        if (i < M) {
+            const int64_t o = (int64_t)list[kk] * Mp + i;
+            const float2 lo = xlo[o];
+            double2 hi = xhi[o];
+            hi.x += (double)lo.x;
+            hi.y += (double)lo.y;
+            xhi[o] = hi;
+            xlo[o] = make_float2(0.f, 0.f);
+        }
+    }
+}
+
+// rho = b - (z S - H) x in FP64 with FP64 blocks (b = e_bl); returns ||rho||^2
+// (reduced over the workgroup).  Uses q as scratch.
+template <int BD, int NT, bool SID>
+__device__ double true_residual(const KParams& P, const Sys& sy, zc z, const double2* x, double2* q,
+                                double2* rho, int bl, double* red) {
+    __syncthreads();
+    (void)op_apply<BD, NT, double, double, SID>(P.Hv64, P.Sv64, sy, z, x, q);
+    double nn[1] = {0.0};
+    for (int i = threadIdx.x; i < sy.M; i += NT) {
+        const zc qv = ld<double>(q, i);
+        const zc v = zmk((i == bl ? 1.0 : 0.0) - qv.re, -qv.im);
+        st<double>(rho, i, v);
+        nn[0] += v.re * v.re + v.im * v.im;
+    }
+    block_sum<NT, 1>(nn, red);
+    return nn[0];
+}
+
+// Single-shift FP64 COCG for (z S - H) x = b started from the given x, whose
+// residual rho (and ||rho||^2 = nr2) is already in place.  Converges when
+// ||rho|| < tol ||b||.  Returns the iterations used (negative if it stopped
+// on a breakdown).
+template <int BD, int NT, bool SID>
+__device__ int fallback_cocg(const KParams& P, const Sys& sy, zc z, double2* x, double2* rho, double2* r,
+                             double2* p, double2* q, double2* res, double2* d, double2* w, double nr2,
+                             int maxit, double* red) {
+    const int M = sy.M;
+    double2* rr = SID ? rho : r;
+    if (!SID) (void)inner_cg<BD, NT, double, double>(P.Sv64, sy, rho, rr, res, d, w, nr2, P.inner_tol,
+                                                     P.inner_maxiter, red);
+    double g[2] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < M; i += NT) {
+        const zc t = zmul(ld<double>(rho, i), ld<double>(rr, i));
+        g[0] += t.re;
+        g[1] += t.im;
+        p[i] = rr[i];
+    }
+    block_sum<NT, 2>(g, red);
+    zc gamma = zmk(g[0], g[1]);
+    const double stop = P.tol;   // ||b|| = 1
+    int it = 0;
+    for (; it < maxit; ++it) {
+        if (sqrt(nr2) < stop) break;
+        const zc mup = op_apply<BD, NT, double, double, SID>(P.Hv64, P.Sv64, sy, z, p, q);
+        double m2[2] = {mup.re, mup.im};
+        block_sum<NT, 2>(m2, red);
+        const zc mu = zmk(m2[0], m2[1]);
+        if (!zfinite(mu) || zzero(mu)) return -1 - it;
+        const zc alpha = zdiv(gamma, mu);
+        double nn[1] = {0.0};
+        for (int i = threadIdx.x; i < M; i += NT) {
+            const zc pv = ld<double>(p, i);
+            st<double>(x, i, zadd(ld<double>(x, i), zmul(alpha, pv)));
+            const zc v = zsub(ld<double>(rho, i), zmul(alpha, ld<double>(q, i)));
+            st<double>(rho, i, v);
+            nn[0] += v.re * v.re + v.im * v.im;
+        }
+        block_sum<NT, 1>(nn, red);
+        nr2 = nn[0];
+        if (!SID) (void)inner_cg<BD, NT, double, double>(P.Sv64, sy, rho, rr, res, d, w, nr2, P.inner_tol,
+                                                         P.inner_maxiter, red);
+        double gn[2] = {0.0, 0.0};
+        for (int i = threadIdx.x; i < M; i += NT) {
+            const zc t = zmul(ld<double>(rho, i), ld<double>(rr, i));
+            gn[0] += t.re;
+            gn[1] += t.im;
+        }
+        block_sum<NT, 2>(gn, red);
+        const zc gnew = zmk(gn[0], gn[1]);
+        if (!zfinite(gnew) || zzero(gamma)) return -1 - it;
+        const zc beta = zdiv(gnew, gamma);
+        gamma = gnew;
+        for (int i = threadIdx.x; i < M; i += NT)
+            st<double>(p, i, zadd(ld<double>(rr, i), zmul(beta, ld<double>(p, i))));
+        __syncthreads();
+    }
+    return it;
+}
+
+// Bytes of one workgroup slot for K shifts and Mp padded rows.
+__host__ __device__ inline int64_t slot_bytes_for(int K, int64_t Mp, bool lo) {
+    const int64_t b = lo ? (32 * (int64_t)K + 6 * 8 + 7 * 16) * Mp : (32 * (int64_t)K + 7 * 16) * Mp;
+    return (b + 255) / 256 * 256;
+}
+
 template <int BD, int NT, class TV, class TB, bool SID>
 __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
+    constexpr bool LO = sizeof(TV) == 4;
     const int tid = threadIdx.x;
     const int K = P.K;
     const RhsInfo ri = P.rhs[rj];
@@ -335,31 +443,61 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
     sy.M = si.nrows * BD;
     const int M = sy.M;
     const int64_t Mp = P.Mp;
+    const TB* Hb = (const TB*)P.Hv;
+    const TB* Sb = (const TB*)P.Sv;
 
-    v2<TV>* x = (v2<TV>*)ws;
+    // ---- per-slot working memory
+    v2<TV>* x = (v2<TV>*)ws;                    // FP64: x; FP32 forms: x_lo
     v2<TV>* p = x + (int64_t)K * Mp;
-    v2<TV>* rho = p + (int64_t)K * Mp;
+    double2* xhi;                                // FP64 solution accumulator
+    v2<TV>* vbase;
+    if constexpr (LO) {
+        xhi = (double2*)(p + (int64_t)K * Mp);
+        vbase = (v2<TV>*)(xhi + (int64_t)K * Mp);
+    } else {
+        xhi = (double2*)x;
+        vbase = p + (int64_t)K * Mp;
+    }
+    v2<TV>* rho = vbase;
     v2<TV>* rbuf = rho + Mp;
     v2<TV>* q = rbuf + Mp;
     v2<TV>* res = q + Mp;
     v2<TV>* d = res + Mp;
     v2<TV>* w = d + Mp;
     v2<TV>* r = SID ? rho : rbuf;    // S = I: r = S^{-1} rho = rho
+    // FP64 vectors for replacement, audit and fallback
+    double2 *rho64, *r64, *q64, *res64, *d64, *w64, *p64;
+    if constexpr (LO) {
+        rho64 = (double2*)(w + Mp);
+        r64 = rho64 + Mp;
+        q64 = r64 + Mp;
+        res64 = q64 + Mp;
+        d64 = res64 + Mp;
+        w64 = d64 + Mp;
+        p64 = w64 + Mp;
+    } else {
+        rho64 = (double2*)rho;
+        r64 = (double2*)rbuf;
+        q64 = (double2*)q;
+        res64 = (double2*)res;
+        d64 = (double2*)d;
+        w64 = (double2*)w;
+        p64 = (double2*)(w + Mp);
+    }
 
     const int maxiter = P.maxiter > 0 ? P.maxiter : max(1000, 4 * M);
-    const double itol = sizeof(TV) == 8 ? P.inner_tol : P.inner_tol_lo;
+    const double itol = LO ? P.inner_tol_lo : P.inner_tol;
     const double nu0 = 1.0;   // ||e_j||
-    int64_t inner_total = 0, sum_upd = 0, nswitch = 0;
+    int64_t inner_total = 0, sum_upd = 0, nswitch = 0, nrepl = 0, nfb = 0;
 
     // ---- init: rho = e_j, r = S^{-1} rho, gamma = rho^T r, x_k = 0, p_k = r
     for (int i = tid; i < M; i += NT) st<TV>(rho, i, zmk(i == ri.b_local ? 1.0 : 0.0, 0.0));
     __syncthreads();
-    if constexpr (!SID) inner_total += inner_cg<BD, NT, TV, TB>(P, sy, rho, r, res, d, w, 1.0, itol,
+    if constexpr (!SID) inner_total += inner_cg<BD, NT, TV, TB>(Sb, sy, rho, r, res, d, w, 1.0, itol,
                                                                 P.inner_maxiter, L.red);
     double gp[2] = {0.0, 0.0};
     for (int i = tid; i < M; i += NT) {
-        const zc a = ld<TV>(rho, i), b = ld<TV>(r, i);
-        const zc t = zmul(a, b);
+        const zc t = zmul(ld<TV>(rho, i), ld<TV>(r, i));
         gp[0] += t.re;
         gp[1] += t.im;
     }
@@ -372,8 +510,9 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
         L.stat[k] = ST_MAXITER;
         L.iters[k] = -1;
         L.resid[k] = INFINITY;
+        L.dirty[k] = 0;
     }
-    shift_init<NT, TV>(x, p, r, M, Mp, K);
+    shift_init<NT, TV>(x, p, LO ? xhi : nullptr, r, M, Mp, K);
     __syncthreads();
 
     int s = P.seed0;
@@ -384,7 +523,7 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
         n_outer = n + 1;
         const zc zs = zmk(P.z[2 * s], P.z[2 * s + 1]);
         // ---- q = (z_s S - H) p_s, mu = p_s^T q
-        const zc mup = op_apply<BD, NT, TV, TB, SID>(P, sy, zs, p + (int64_t)s * Mp, q);
+        const zc mup = op_apply<BD, NT, TV, TB, SID>(Hb, Sb, sy, zs, p + (int64_t)s * Mp, q);
         double mr[2] = {mup.re, mup.im};
         block_sum<NT, 2>(mr, L.red);
         const zc mu = zmk(mr[0], mr[1]);
@@ -398,15 +537,14 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
         // ---- rho -= alpha q;  nu^2 = ||rho||^2
         double nn[1] = {0.0};
         for (int i = tid; i < M; i += NT) {
-            const zc a = zsub(ld<TV>(rho, i), zmul(alpha, ld<TV>(q, i)));
-            st<TV>(rho, i, a);
+            st<TV>(rho, i, zsub(ld<TV>(rho, i), zmul(alpha, ld<TV>(q, i))));
             const zc b = ld<TV>(rho, i);
             nn[0] += b.re * b.re + b.im * b.im;
         }
         block_sum<NT, 1>(nn, L.red);
         const double nu = sqrt(nn[0]);
         // ---- r = S^{-1} rho
-        if constexpr (!SID) inner_total += inner_cg<BD, NT, TV, TB>(P, sy, rho, r, res, d, w, nn[0], itol,
+        if constexpr (!SID) inner_total += inner_cg<BD, NT, TV, TB>(Sb, sy, rho, r, res, d, w, nn[0], itol,
                                                                     P.inner_maxiter, L.red);
         // ---- gamma' = rho^T r
         double gn[2] = {0.0, 0.0};
@@ -448,6 +586,7 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
             const double est = nu / zabs(pin);
             L.resid[k] = est / nu0;
             L.updf[k] = 1;
+            L.dirty[k] = 1;
             if (est < P.tol * nu0) {
                 L.done[k] = 1;
                 L.stat[k] = ST_CONVERGED;
@@ -455,7 +594,7 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
             }
         }
         __syncthreads();
-        compact<NT>(L, K);
+        compact_flags(L.updf, L.done, K, L.upd, &L.ctl[0], &L.ctl[1]);
         __syncthreads();
         const int nupd = L.ctl[0];
         const int ndone = L.ctl[1];
@@ -480,12 +619,10 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
             const zc ratio = zdiv(co, cn);
             alpha_n = zmul(ratio, alpha);
             beta_n = zmul(zmul(ratio, ratio), beta);
-            const zc icn = zdiv(zmk(1.0, 0.0), cn);
             for (int i = tid; i < M; i += NT) {
                 st<TV>(rho, i, zdiv(ld<TV>(rho, i), cn));
                 if constexpr (!SID) st<TV>(r, i, zdiv(ld<TV>(r, i), cn));
             }
-            (void)icn;
             gamma = zdiv(gamma, zmul(cn, cn));
             for (int k = tid; k < K; k += NT) {
                 if (!L.done[k]) {
@@ -497,21 +634,78 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
             ++nswitch;
             __syncthreads();
         }
+        if constexpr (LO) {
+            if (P.replace_every > 0 && (n + 1) % P.replace_every == 0) {
+                // ---- group-wise x update, then FP64 residual replacement on the seed
+                compact_flags(L.dirty, nullptr, K, L.upd, &L.ctl[3], nullptr);
+                __syncthreads();
+                const int nd = L.ctl[3];
+                flush_lo<NT>((float2*)x, xhi, M, Mp, L.upd, nd);
+                __syncthreads();
+                for (int k = tid; k < K; k += NT) L.dirty[k] = 0;
+                const zc z2 = zmk(P.z[2 * s], P.z[2 * s + 1]);
+                const double nr2 = true_residual<BD, NT, SID>(P, sy, z2, xhi + (int64_t)s * Mp, q64, rho64,
+                                                              ri.b_local, L.red);
+                double2* rr64 = SID ? rho64 : r64;
+                if constexpr (!SID) inner_total += inner_cg<BD, NT, double, double>(P.Sv64, sy, rho64, rr64, res64,
+                                                                                    d64, w64, nr2, P.inner_tol,
+                                                                                    P.inner_maxiter, L.red);
+                double g2[2] = {0.0, 0.0};
+                for (int i = tid; i < M; i += NT) {
+                    const zc a = ld<double>(rho64, i), b = ld<double>(rr64, i);
+                    const zc t = zmul(a, b);
+                    g2[0] += t.re;
+                    g2[1] += t.im;
+                    st<TV>(rho, i, a);
+                    if constexpr (!SID) st<TV>(r, i, b);
+                }
+                block_sum<NT, 2>(g2, L.red);
+                gamma = zmk(g2[0], g2[1]);
+                ++nrepl;
+            }
+        }
         alpha_prev = alpha_n;
         beta_prev = beta_n;
     }
     __syncthreads();
+    if constexpr (LO) {
+        compact_flags(L.dirty, nullptr, K, L.upd, &L.ctl[3], nullptr);
+        __syncthreads();
+        flush_lo<NT>((float2*)x, xhi, M, Mp, L.upd, L.ctl[3]);
+        __syncthreads();
+    }
 
-    // ---- outputs: G rows (or all of x), iteration counts, codes, estimates
+    // ---- FP64 true-residual audit of every shift, FP64 fallback where needed
+    if (P.audit > 0) {
+        const bool fix = LO || P.audit >= 2;
+        for (int k = 0; k < K; ++k) {
+            const zc zk = zmk(P.z[2 * k], P.z[2 * k + 1]);
+            double2* xk = xhi + (int64_t)k * Mp;
+            double nr2 = true_residual<BD, NT, SID>(P, sy, zk, xk, q64, rho64, ri.b_local, L.red);
+            const bool retry = L.stat[k] == ST_CONVERGED || L.stat[k] == ST_MAXITER;
+            if (fix && retry && !(sqrt(nr2) <= P.tol)) {
+                const int it = fallback_cocg<BD, NT, SID>(P, sy, zk, xk, rho64, r64, p64, q64, res64, d64, w64,
+                                                          nr2, maxiter, L.red);
+                nfb += it < 0 ? -it : it;
+                nr2 = true_residual<BD, NT, SID>(P, sy, zk, xk, q64, rho64, ri.b_local, L.red);
+                // the audited residual is the judge: converged only if it is <= tol
+                if (tid == 0) L.stat[k] = it < 0 ? ST_BREAKDOWN : (sqrt(nr2) <= P.tol ? ST_CONVERGED : ST_MAXITER);
+            }
+            if (tid == 0) L.resid[k] = sqrt(nr2);
+        }
+        __syncthreads();
+    }
+
+    // ---- outputs: G rows (or all of x), iteration counts, codes, residuals
     const int nout = ri.full_x ? M : ri.nout;
     const int64_t obase = P.out_off[rj] * (int64_t)K;
     const int32_t* ol = P.out_local + ri.out_base;
     for (int64_t idx = tid; idx < (int64_t)K * nout; idx += NT) {
         const int k = (int)(idx / nout), o = (int)(idx - (int64_t)k * nout);
         const int row = ri.full_x ? o : ol[o];
-        const zc v = ld<TV>(x + (int64_t)k * Mp, row);
-        P.out[2 * (obase + idx)] = v.re;
-        P.out[2 * (obase + idx) + 1] = v.im;
+        const double2 v = xhi[(int64_t)k * Mp + row];
+        P.out[2 * (obase + idx)] = v.x;
+        P.out[2 * (obase + idx) + 1] = v.y;
     }
     for (int k = tid; k < K; k += NT) {
         const int64_t o = (int64_t)rj * K + k;
@@ -527,8 +721,8 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
         st_[3] = nswitch;
         st_[4] = M;
         st_[5] = sy.rowptr[sy.nrows] - sy.rowptr[0];
-        st_[6] = 0;
-        st_[7] = 0;
+        st_[6] = nrepl;
+        st_[7] = nfb;
     }
     __syncthreads();
 }
@@ -591,6 +785,8 @@ bool supported_bdim(int bd) { return bd == 1 || bd == 4 || bd == 9; }
 
 size_t solver_lds_bytes(int K, int nt) { return lds_bytes(K, nt); }
 
+int64_t solver_slot_bytes(int K, int64_t Mp, int prec) { return slot_bytes_for(K, Mp, prec != 0); }
+
 hipError_t launch_solver(const KParams& P, int bd, int prec, bool sid, int nt, int slots, hipStream_t st) {
     switch (bd) {
         case 1: return launch_nt<1>(P, prec, sid, nt, slots, st);
@@ -601,6 +797,7 @@ hipError_t launch_solver(const KParams& P, int bd, int prec, bool sid, int nt, i
 }
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st) {
+
     if (n <= 0) return hipSuccess;
     const int blocks = (int)std::min<int64_t>((n + 255) / 256, 1024);
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(256), 0, st, p, v, n);

@@ -53,7 +53,7 @@ struct KParams {
     int32_t audit;             // FP32 forms
     int32_t s_unit_diag;       // S's diagonal blocks are exactly I
     // work queue and per-workgroup memory
-    int32_t* queue;
+    int32_t* queue;            // next RHS to hand out
     char* ws;
     int64_t slot_bytes;
     int64_t Mp;                // padded max cluster dimension (elements)

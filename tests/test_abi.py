@@ -45,7 +45,7 @@ def test_header_compiles_as_c():
 def test_options_default():
     o = B.scocg_options_default()
     assert o.tol == 1e-10 and o.maxiter == 0 and o.precision == B.FP64
-    assert o.replace_every == 20 and o.inner_tol == 1e-13 and o.seed_index == -1 and o.audit == 1
+    assert o.replace_every == 0 and o.inner_tol == 1e-13 and o.seed_index == -1 and o.audit == 1
 
 
 def _bsr(p):
