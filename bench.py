@@ -34,57 +34,63 @@ WORKLOADS = {
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 
-def algorithmic_bytes(stats, K, bd, has_S, prec, audit):
-    """Bytes the method must move per launch (see the design notes):
-    per outer iteration the per-shift sweep reads and writes x_k and p_k of
-    every updated shift and reads r once; the seed operator reads the H and S
-    blocks of the local pattern, p_s, and writes q; the seed vector updates
-    touch rho, q, r; each inner-CG iteration reads the S blocks and streams
-    its four vectors; the audit applies each shift's operator once."""
+def algorithmic_bytes(stats, nout, K, bd, has_S, prec, projected, w_share, audit):
+    """Algorithmic bytes of one launch, from the per-unit figures of the
+    design notes (FP64; FP32 halves vectors, blocks shrink to 4 or 2 bytes).
+    Per RHS and outer iteration:
+      sweep  64 K_a n + 16 n        n = M_j (full x) or |I_j| (projected rows)
+      A4     (nb_H + nb_S) b^2 8 / w_share + 32 M_j
+      A5     k_in ((nb_S b^2 8) / w_share + 96 M_j)
+    with w_share the number of RHS sharing the blocks at once (all resident
+    RHS for a global system, 1 for order-N clusters); the audit applies each
+    shift's operator once."""
     vb = 16 if prec == 0 else 8
     bb = {0: 8, 1: 4, 2: 2}[prec]
     outer, sum_upd, inner = stats[:, 0].astype(float), stats[:, 1].astype(float), stats[:, 2].astype(float)
     M, nblk = stats[:, 4].astype(float), stats[:, 5].astype(float)
+    n = np.asarray(nout, dtype=float) if projected else M
     blk = nblk * bd * bd * bb
-    op = blk * (2 if has_S else 1) + 2 * M * vb
-    sweep = sum_upd * M * 4 * vb + outer * M * vb
-    seedvec = outer * 5 * M * vb
-    inner_b = inner * (blk + 8 * M * vb) if has_S else 0.0
-    aud = K * (nblk * bd * bd * 8 * (2 if has_S else 1) + 2 * M * 16) if audit else 0.0
-    return float(np.sum(sweep + outer * op + seedvec + inner_b + aud))
+    nmat = 2 if has_S else 1
+    sweep = sum_upd * n * 4 * vb + outer * n * vb
+    a4 = outer * (blk * nmat / w_share + 2 * vb * M)
+    a5 = inner * (blk / w_share + 6 * vb * M) if has_S else 0.0
+    aud = K * (nblk * bd * bd * 8 * nmat / w_share + 32 * M) if (audit and not projected) else 0.0
+    return float(np.sum(sweep + a4 + a5 + aud))
 
 
-def cpu_baseline(prob, gpu_stats, n_rhs_sample, iters_sample, workers):
+def cpu_baseline(prob, gpu_stats, n_rhs_sample, iters_sample, workers, projected):
     """Time the oracle (as it stands) on host cores: `workers` processes, each
-    running `iters_sample` outer iterations of one RHS of the same workload;
-    the measured time per iteration times the mean outer iteration count the
-    solve needs (from the GPU run) gives the time per RHS, hence solves/s."""
+    running `iters_sample` outer iterations of one RHS of the same workload
+    with the same form of the method (projected rows or full x); the measured
+    time per iteration times the mean outer iteration count the solve needs
+    (from the GPU run) gives the time per RHS, hence solves/s."""
     import multiprocessing as mp
     idx = list(range(min(n_rhs_sample, prob.nrhs)))
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(workers) as pool:
-        per = pool.map(_cpu_worker, [(prob, j, iters_sample) for j in idx])
+        per = pool.map(_cpu_worker, [(prob, j, iters_sample, projected) for j in idx])
     wall = time.perf_counter() - t0
     t_iter = float(np.mean(per))                 # seconds per outer iteration, one process
     mean_outer = float(np.mean(gpu_stats[:, 0]))
     t_rhs = t_iter * mean_outer
     rate = prob.nshift * min(workers, len(idx)) / t_rhs
     return dict(value=rate, unit="solves/s", cores=int(min(workers, len(idx))), kind="oracle",
-                sample=f"{len(idx)} RHS x {iters_sample} outer iterations of the same workload, one RHS per "
+                sample=f"{len(idx)} RHS x {iters_sample} outer iterations of the same workload "
+                       f"({'projected rows, three-term form' if projected else 'full x'}), one RHS per "
                        f"process ({workers} processes, 1 BLAS thread each); t/iteration {t_iter * 1e3:.1f} ms "
                        f"x mean outer iterations {mean_outer:.0f} (GPU run) = {t_rhs:.0f} s per RHS of "
                        f"{prob.nshift} shifts; wall {wall:.1f} s")
 
 
 def _cpu_worker(args):
-    prob, j, iters = args
+    prob, j, iters, projected = args
     try:
         from threadpoolctl import threadpool_limits
         threadpool_limits(1)
     except Exception:
         pass
-    from oracle import local_system, scocg
+    from oracle import local_system, scocg, scocg_projected
     from synth import bsr_to_scipy
     H = bsr_to_scipy(prob.H)
     S = bsr_to_scipy(prob.S) if prob.S is not None else None
@@ -92,8 +98,50 @@ def _cpu_worker(args):
     b = np.zeros(orb.size, dtype=np.complex128)
     b[loc] = 1.0
     t0 = time.perf_counter()
-    res = scocg(Hc, Sc, prob.shifts, b, 1e-6, maxiter=iters)
+    if projected:
+        rows = np.searchsorted(orb, prob.outs(j))
+        res = scocg_projected(Hc, Sc, prob.shifts, b, rows, 1e-6, maxiter=iters)
+    else:
+        res = scocg(Hc, Sc, prob.shifts, b, 1e-6, maxiter=iters)
     return (time.perf_counter() - t0) / max(1, res.n_outer)
+
+
+def copy_calibration(nbytes):
+    """A plain device copy of known size (for scaling FETCH_SIZE / WRITE_SIZE)."""
+    import torch
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"copy_bytes": n * 8, "seconds": dt, "GB/s": 2 * n * 8 / dt / 1e9}), flush=True)
+
+
+def _kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("scocg_kernels.hip", "scocg_device.hpp", "scocg_params.hpp"):
+        with open(os.path.join(ROOT, "paper_1402_7285_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(args, projected):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this workload (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading),
+    or None if there is none or the kernel sources changed since."""
+    key = f"{args.workload}_{args.precision}_{'proj' if projected else 'full'}"
+    path = os.path.join(ROOT, "profiles", f"k_scocg_{key}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_hash") != _kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
 
 
 def main():
@@ -110,7 +158,12 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=60)
     ap.add_argument("--cpu-rhs", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--projected", type=int, default=1, help="FP64 SELECTED_G: rows-only solve (default 1)")
+    ap.add_argument("--copy-calib", type=int, default=0, help="only run a device copy of this many bytes")
     args = ap.parse_args()
+    if args.copy_calib:
+        copy_calibration(args.copy_calib)
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the solver shards over RHS with no "
@@ -131,7 +184,8 @@ def main():
     if prob.cluster_ptr is not None:
         kw.update(cluster_ptr=prob.cluster_ptr, cluster_atoms=prob.cluster_atoms)
     plan = B.Plan(P, prob.shifts, prob.rhs, tol=args.tol, precision=PREC[args.precision], audit=1,
-                  threads=args.threads, slots=args.slots, **kw)
+                  threads=args.threads, slots=args.slots, projected=args.projected, **kw)
+    projected = bool(plan.info["global"] & 2)
     bufs = plan.alloc_outputs()
     stream = torch.cuda.current_stream()
     for w in range(args.warmup):
@@ -156,8 +210,12 @@ def main():
     stats = plan.stats()
     ms_per_step = wall / args.steps * 1e3
     value = good / (ms_per_step / 1e3)
-    alg = algorithmic_bytes(stats, prob.nshift, prob.bdim, prob.S is not None, PREC[args.precision], True)
+    nout = np.diff(prob.out_ptr)
+    w_share = min(plan.info["slots"], prob.nrhs) if prob.cluster_ptr is None else 1
+    alg = algorithmic_bytes(stats, nout, prob.nshift, prob.bdim, prob.S is not None, PREC[args.precision],
+                            projected, w_share, True)
     achieved = alg / kernel_s / 1e9
+    traffic = measured_traffic(args, projected)
     out = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
@@ -165,20 +223,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {wl['desc']}", "nrhs": prob.nrhs, "shifts": prob.nshift,
                    "M": prob.M, "tol": args.tol, "precision": args.precision, "batched": "persistent",
-                   "slots": plan.info["slots"], "threads": plan.info["threads"]},
+                   "slots": plan.info["slots"], "threads": plan.info["threads"],
+                   "form": "projected rows (three-term seed)" if projected else "full x"},
         "converged_pairs": good, "pairs": int(status.size),
         "outer_iterations": {"mean": float(stats[:, 0].mean()), "max": int(stats[:, 0].max())},
         "inner_per_outer": float(stats[:, 2].sum() / max(1, stats[:, 0].sum())),
         "fallback_iterations": int(stats[:, 7].sum()),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_scocg (persistent solver)", "kernel_ms": kernel_s * 1e3,
                      "algorithmic_bytes": alg},
     }
     if not args.no_cpu_baseline:
         workers = max(1, min(16, os.cpu_count() or 1))
         print(f"[bench] cpu baseline: oracle on {workers} processes ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(prob, stats, args.cpu_rhs, args.cpu_iters, workers)
+        out["cpu_baseline"] = cpu_baseline(prob, stats, args.cpu_rhs, args.cpu_iters, workers, projected)
     print(json.dumps(out), flush=True)
 
 

@@ -144,10 +144,15 @@ typedef struct {
                                With the audit on, resid holds the audited residual,
                                and a re-solved pair is CONVERGED only if its audited
                                residual is <= tol (MAXITER otherwise). */
+    int32_t projected;      /* FP64 with SELECTED_G output: keep x_k, p_k only on the
+                               requested rows and run the seed in the three-term form
+                               (per-shift work O(rows) instead of O(M_j); no audit,
+                               resid is the recursive estimate).  Default 1. */
 } scocg_options;
 
 /* Defaults: tol 1e-10, maxiter 0, FP64, replace_every 0, inner_maxiter 1000,
- * inner_tol 1e-13, inner_tol_lo 1e-6, seed_index -1, threads 0, slots 0, audit 1. */
+ * inner_tol 1e-13, inner_tol_lo 1e-6, seed_index -1, threads 0, slots 0, audit 1,
+ * projected 1. */
 void scocg_options_default(scocg_options* opt);
 
 /* ---- right-hand sides ----------------------------------------------------- */
@@ -202,7 +207,7 @@ int64_t scocg_plan_out_count(const scocg_plan* plan);
  * Launch shape of a plan, host int64[SCOCG_NINFO]: [0] resident workgroups,
  * [1] threads per workgroup, [2] padded rows per workgroup slot, [3] bytes of
  * one slot, [4] initial seed index, [5] LDS bytes per workgroup,
- * [6] precision, [7] 1 if every RHS uses the whole system.
+ * [6] precision, [7] bit 0: every RHS uses the whole system; bit 1: projected.
  */
 #define SCOCG_NINFO 8
 scocg_status scocg_plan_info(const scocg_plan* plan, int64_t* info);

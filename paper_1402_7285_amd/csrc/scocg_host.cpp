@@ -107,6 +107,8 @@ struct scocg_plan {
     scocg_options opt{};
     int32_t K = 0, nrhs = 0, seed0 = 0;
     int nt = 512, slots = 0, prec = 0;
+    bool proj = false;        // projected (requested rows only) FP64 solve
+    int64_t nIp = 0;
     int64_t Mp = 0, slot_bytes = 0, out_count = 0;
     std::vector<int64_t> out_off;
     // device arrays owned by the plan
@@ -372,6 +374,7 @@ extern "C" void scocg_options_default(scocg_options* o) {
     o->threads = 0;
     o->slots = 0;
     o->audit = 1;
+    o->projected = 1;
 }
 
 // Initial seed: smallest |Im z|, then Re z closest to the median of Re z
@@ -643,7 +646,15 @@ extern "C" scocg_status scocg_plan_create(scocg_problem* P, const scocg_options*
     pl->out_count = hm.outoff[nrhs] * (int64_t)nshift;
     pl->nt = opt.threads ? opt.threads : 512;
     pl->Mp = std::max<int64_t>(64, (hm.maxM + 63) / 64 * 64);
-    pl->slot_bytes = scocg::solver_slot_bytes(nshift, pl->Mp, opt.precision);
+    pl->proj = opt.projected && opt.precision == SCOCG_FP64 && !(spec && spec->out_mode == SCOCG_OUT_FULL_X);
+    if (pl->proj) {
+        int64_t maxout = 1;
+        for (const auto& r : hm.rhs) maxout = std::max<int64_t>(maxout, r.nout);
+        pl->nIp = (maxout + 63) / 64 * 64;
+        pl->slot_bytes = scocg::solver_slot_bytes_proj(nshift, pl->Mp, pl->nIp);
+    } else {
+        pl->slot_bytes = scocg::solver_slot_bytes(nshift, pl->Mp, opt.precision);
+    }
 
     auto bail = [&](scocg_status e) { scocg_plan_free(pl); return e; };
     int cus = 0;
@@ -708,7 +719,7 @@ extern "C" scocg_status scocg_plan_info(const scocg_plan* pl, int64_t* info) {
     info[4] = pl->seed0;
     info[5] = (int64_t)scocg::solver_lds_bytes(pl->K, pl->nt);
     info[6] = pl->prec;
-    info[7] = pl->global ? 1 : 0;
+    info[7] = (pl->global ? 1 : 0) | (pl->proj ? 2 : 0);
     return SCOCG_OK;
 }
 
@@ -764,6 +775,7 @@ extern "C" scocg_status scocg_plan_run(scocg_plan* pl, void* stream, scocg_z* ou
     k.ws = pl->dws;
     k.slot_bytes = pl->slot_bytes;
     k.Mp = pl->Mp;
+    k.nIp = pl->nIp;
     k.out = (double*)out;
     k.iters = iters;
     k.status = status;
@@ -771,7 +783,7 @@ extern "C" scocg_status scocg_plan_run(scocg_plan* pl, void* stream, scocg_z* ou
     k.stats = pl->dstats;
     (void)hipGetLastError();   // drop any error another caller left on this thread
     HIP_TRY(scocg::launch_fill_i32(pl->dqueue, 0, 1, st));
-    HIP_TRY(scocg::launch_solver(k, P->bd, pl->prec, !P->has_S, pl->nt, pl->slots, st));
+    HIP_TRY(scocg::launch_solver(k, P->bd, pl->proj ? 3 : pl->prec, !P->has_S, pl->nt, pl->slots, st));
     return SCOCG_OK;
 }
 

@@ -727,7 +727,248 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
     __syncthreads();
 }
 
-template <int BD, int NT, class TV, class TB, bool SID>
+// Bytes of one workgroup slot in projected mode (FP64): seven vectors of the
+// seed process plus x_k and p_k on the requested rows of every shift.
+__host__ __device__ inline int64_t slot_bytes_proj(int K, int64_t Mp, int64_t nIp) {
+    return ((7 * Mp + 2 * (int64_t)K * nIp) * 16 + 255) / 256 * 256;
+}
+
+// Projected solve of one RHS: x_k and p_k live only on the rows whose G
+// elements are requested; the seed runs the three-term form of COCG
+//   mu_n = r_n^T q_n - beta_{n-1} gamma_n / alpha_{n-1},   q_n = (z_s S - H) r_n
+//   rho_{n+1} = (1 + c_n) rho_n - alpha_n q_n - c_n rho_{n-1},  c_n = alpha_n beta_{n-1} / alpha_{n-1}
+// so that a seed switch only rescales the two latest residuals.  The shifted
+// scalars and the per-shift updates are those of the two-term form.
+template <int BD, int NT, bool SID>
+__device__ void solve_one_proj(const KParams& P, int rj, char* ws, const Lds& L) {
+    const int tid = threadIdx.x;
+    const int K = P.K;
+    const RhsInfo ri = P.rhs[rj];
+    const SysInfo si = P.sys[ri.sys];
+    Sys sy;
+    sy.rowptr = P.rowptr_l + si.row_base;
+    sy.ecol = P.ecol + si.ent_base;
+    sy.egid = P.egid + si.ent_base;
+    sy.nrows = si.nrows;
+    sy.M = si.nrows * BD;
+    const int M = sy.M;
+    const int64_t Mp = P.Mp, nIp = P.nIp;
+    const double* Hb = (const double*)P.Hv;
+    const double* Sb = (const double*)P.Sv;
+    const int nI = ri.nout;
+    const int32_t* rows = P.out_local + ri.out_base;
+
+    double2* rhoA = (double2*)ws;
+    double2* rhoB = rhoA + Mp;
+    double2* rbuf = rhoB + Mp;
+    double2* q = rbuf + Mp;
+    double2* res = q + Mp;
+    double2* d = res + Mp;
+    double2* w = d + Mp;
+    double2* xI = w + Mp;
+    double2* pI = xI + (int64_t)K * nIp;
+    double2* rho = rhoA;
+    double2* rho_old = rhoB;
+    double2* r = SID ? rho : rbuf;
+
+    const int maxiter = P.maxiter > 0 ? P.maxiter : max(1000, 4 * M);
+    const double nu0 = 1.0;
+    int64_t inner_total = 0, sum_upd = 0, nswitch = 0;
+
+    for (int i = tid; i < M; i += NT) {
+        st<double>(rho, i, zmk(i == ri.b_local ? 1.0 : 0.0, 0.0));
+        st<double>(rho_old, i, zmk(0.0, 0.0));
+    }
+    __syncthreads();
+    if constexpr (!SID) inner_total += inner_cg<BD, NT, double, double>(Sb, sy, rho, r, res, d, w, 1.0, P.inner_tol,
+                                                                        P.inner_maxiter, L.red);
+    double gp[2] = {0.0, 0.0};
+    for (int i = tid; i < M; i += NT) {
+        const zc t = zmul(ld<double>(rho, i), ld<double>(r, i));
+        gp[0] += t.re;
+        gp[1] += t.im;
+    }
+    block_sum<NT, 2>(gp, L.red);
+    zc gamma = zmk(gp[0], gp[1]);
+    for (int k = tid; k < K; k += NT) {
+        L.pi[k] = zmk(1.0, 0.0);
+        L.piold[k] = zmk(1.0, 0.0);
+        L.done[k] = 0;
+        L.stat[k] = ST_MAXITER;
+        L.iters[k] = -1;
+        L.resid[k] = INFINITY;
+    }
+    for (int idx = tid; idx < K * nI; idx += NT) {
+        const int k = idx / nI, o = idx - k * nI;
+        xI[(int64_t)k * nIp + o] = make_double2(0.0, 0.0);
+        pI[(int64_t)k * nIp + o] = r[rows[o]];
+    }
+    __syncthreads();
+
+    int s = P.seed0;
+    zc alpha_prev = zmk(1.0, 0.0), beta_prev = zmk(0.0, 0.0);
+    int n_outer = 0;
+    for (int n = 0; n < maxiter; ++n) {
+        n_outer = n + 1;
+        const zc zs = zmk(P.z[2 * s], P.z[2 * s + 1]);
+        // ---- q = (z_s S - H) r, t = r^T q
+        const zc tp = op_apply<BD, NT, double, double, SID>(Hb, Sb, sy, zs, r, q);
+        double tr[2] = {tp.re, tp.im};
+        block_sum<NT, 2>(tr, L.red);
+        const zc mu = zsub(zmk(tr[0], tr[1]), zdiv(zmul(beta_prev, gamma), alpha_prev));
+        if (!zfinite(mu) || zzero(mu)) {
+            const unsigned char code = zfinite(mu) ? ST_BREAKDOWN : ST_NONFINITE;
+            for (int k = tid; k < K; k += NT)
+                if (!L.done[k]) { L.stat[k] = code; L.done[k] = 1; }
+            break;
+        }
+        const zc alpha = zdiv(gamma, mu);
+        const zc c = zdiv(zmul(alpha, beta_prev), alpha_prev);
+        const zc c1 = zadd(zmk(1.0, 0.0), c);
+        // ---- rho_{n+1} = (1 + c) rho_n - alpha q - c rho_{n-1}, written over rho_{n-1}
+        double nn[1] = {0.0};
+        for (int i = tid; i < M; i += NT) {
+            const zc v = zsub(zsub(zmul(c1, ld<double>(rho, i)), zmul(alpha, ld<double>(q, i))),
+                              zmul(c, ld<double>(rho_old, i)));
+            st<double>(rho_old, i, v);
+            nn[0] += v.re * v.re + v.im * v.im;
+        }
+        {
+            double2* t = rho;
+            rho = rho_old;
+            rho_old = t;
+        }
+        if constexpr (SID) r = rho;
+        block_sum<NT, 1>(nn, L.red);
+        const double nu = sqrt(nn[0]);
+        if constexpr (!SID) inner_total += inner_cg<BD, NT, double, double>(Sb, sy, rho, r, res, d, w, nn[0],
+                                                                            P.inner_tol, P.inner_maxiter, L.red);
+        double gn[2] = {0.0, 0.0};
+        for (int i = tid; i < M; i += NT) {
+            const zc t = zmul(ld<double>(rho, i), ld<double>(r, i));
+            gn[0] += t.re;
+            gn[1] += t.im;
+        }
+        block_sum<NT, 2>(gn, L.red);
+        const zc gamma_new = zmk(gn[0], gn[1]);
+        if (!isfinite(nu) || !zfinite(gamma_new)) {
+            for (int k = tid; k < K; k += NT)
+                if (!L.done[k]) { L.stat[k] = ST_NONFINITE; L.done[k] = 1; }
+            break;
+        }
+        const zc beta = zdiv(gamma_new, gamma);
+        gamma = gamma_new;
+
+        // ---- shift scalars (FP64)
+        const zc c3 = zdiv(zmul(beta_prev, alpha), alpha_prev);
+        for (int k = tid; k < K; k += NT) {
+            L.updf[k] = 0;
+            if (L.done[k]) continue;
+            const zc pk = L.pi[k], po = L.piold[k];
+            const zc dz = zmk(P.z[2 * k] - zs.re, P.z[2 * k + 1] - zs.im);
+            const zc f = zadd(zmk(1.0, 0.0), zmul(alpha, dz));
+            const zc pin = zadd(zmul(f, pk), zmul(c3, zsub(pk, po)));
+            if (!zfinite(pin) || zzero(pin)) {
+                L.stat[k] = zfinite(pin) ? ST_BREAKDOWN : ST_NONFINITE;
+                L.done[k] = 1;
+                continue;
+            }
+            const zc ratio = zdiv(pk, pin);
+            L.ca[k] = zmul(ratio, alpha);
+            L.cb[k] = zmul(zmul(ratio, ratio), beta);
+            L.cr[k] = zdiv(zmk(1.0, 0.0), pin);
+            L.piold[k] = pk;
+            L.pi[k] = pin;
+            const double est = nu / zabs(pin);
+            L.resid[k] = est / nu0;
+            L.updf[k] = 1;
+            if (est < P.tol * nu0) {
+                L.done[k] = 1;
+                L.stat[k] = ST_CONVERGED;
+                L.iters[k] = n + 1;
+            }
+        }
+        __syncthreads();
+        compact_flags(L.updf, L.done, K, L.upd, &L.ctl[0], &L.ctl[1]);
+        __syncthreads();
+        const int nupd = L.ctl[0];
+        const int ndone = L.ctl[1];
+        sum_upd += nupd;
+        // ---- x_k += alpha_k p_k;  p_k = r/pi_k + beta_k p_k  on the requested rows
+        for (int idx = tid; idx < nupd * nI; idx += NT) {
+            const int kk = idx / nI, o = idx - kk * nI;
+            const int k = L.upd[kk];
+            const int64_t a = (int64_t)k * nIp + o;
+            const zc pv = ld<double>(pI, a);
+            st<double>(xI, a, zadd(ld<double>(xI, a), zmul(L.ca[k], pv)));
+            st<double>(pI, a, zadd(zmul(L.cr[k], ld<double>(r, rows[o])), zmul(L.cb[k], pv)));
+        }
+        __syncthreads();
+        if (zzero(gamma) && nu > 0.0 && ndone < K) {
+            for (int k = tid; k < K; k += NT)
+                if (!L.done[k]) { L.stat[k] = ST_BREAKDOWN; L.done[k] = 1; }
+            break;
+        }
+        if (ndone == K) break;
+        zc alpha_n = alpha, beta_n = beta;
+        if (L.done[s]) {
+            pick_seed(L, K);
+            __syncthreads();
+            const int s2 = L.ctl[2];
+            const zc cn = L.pi[s2], co = L.piold[s2];
+            __syncthreads();
+            const zc ratio = zdiv(co, cn);
+            alpha_n = zmul(ratio, alpha);
+            beta_n = zmul(zmul(ratio, ratio), beta);
+            for (int i = tid; i < M; i += NT) {
+                st<double>(rho, i, zdiv(ld<double>(rho, i), cn));
+                st<double>(rho_old, i, zdiv(ld<double>(rho_old, i), co));
+                if constexpr (!SID) st<double>(r, i, zdiv(ld<double>(r, i), cn));
+            }
+            gamma = zdiv(gamma, zmul(cn, cn));
+            for (int k = tid; k < K; k += NT) {
+                if (!L.done[k]) {
+                    L.pi[k] = zdiv(L.pi[k], cn);
+                    L.piold[k] = zdiv(L.piold[k], co);
+                }
+            }
+            s = s2;
+            ++nswitch;
+            __syncthreads();
+        }
+        alpha_prev = alpha_n;
+        beta_prev = beta_n;
+    }
+    __syncthreads();
+
+    const int64_t obase = P.out_off[rj] * (int64_t)K;
+    for (int idx = tid; idx < K * nI; idx += NT) {
+        const int k = idx / nI, o = idx - k * nI;
+        const double2 v = xI[(int64_t)k * nIp + o];
+        P.out[2 * (obase + idx)] = v.x;
+        P.out[2 * (obase + idx) + 1] = v.y;
+    }
+    for (int k = tid; k < K; k += NT) {
+        const int64_t o = (int64_t)rj * K + k;
+        if (P.iters) P.iters[o] = L.iters[k];
+        if (P.status) P.status[o] = (int8_t)L.stat[k];
+        if (P.resid) P.resid[o] = L.resid[k];
+    }
+    if (tid == 0 && P.stats) {
+        int64_t* st_ = P.stats + (int64_t)rj * NSTAT;
+        st_[0] = n_outer;
+        st_[1] = sum_upd;
+        st_[2] = inner_total;
+        st_[3] = nswitch;
+        st_[4] = M;
+        st_[5] = sy.rowptr[sy.nrows] - sy.rowptr[0];
+        st_[6] = 0;
+        st_[7] = 0;
+    }
+    __syncthreads();
+}
+
+template <int BD, int NT, class TV, class TB, bool SID, bool PROJ>
 __global__ __launch_bounds__(NT) void k_scocg(KParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_job;
@@ -739,7 +980,8 @@ __global__ __launch_bounds__(NT) void k_scocg(KParams P) {
         const int job = s_job;
         __syncthreads();
         if (job >= P.nrhs) break;
-        solve_one<BD, NT, TV, TB, SID>(P, P.order[job], ws, L);
+        if constexpr (PROJ) solve_one_proj<BD, NT, SID>(P, P.order[job], ws, L);
+        else solve_one<BD, NT, TV, TB, SID>(P, P.order[job], ws, L);
     }
 }
 
@@ -757,15 +999,17 @@ __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
 
 namespace scocg {
 
-template <int BD, int NT, class TV, class TB, bool SID>
+template <int BD, int NT, class TV, class TB, bool SID, bool PROJ = false>
 static hipError_t launch_one(const KParams& P, int slots, hipStream_t st) {
     const size_t lds = lds_bytes(P.K, NT);
-    hipLaunchKernelGGL((k_scocg<BD, NT, TV, TB, SID>), dim3(slots), dim3(NT), lds, st, P);
+    hipLaunchKernelGGL((k_scocg<BD, NT, TV, TB, SID, PROJ>), dim3(slots), dim3(NT), lds, st, P);
     return hipGetLastError();
 }
 
 template <int BD, int NT>
 static hipError_t launch_prec(const KParams& P, int prec, bool sid, int slots, hipStream_t st) {
+    if (prec == 3) return sid ? launch_one<BD, NT, double, double, true, true>(P, slots, st)
+                              : launch_one<BD, NT, double, double, false, true>(P, slots, st);
     if (prec == 0) return sid ? launch_one<BD, NT, double, double, true>(P, slots, st)
                               : launch_one<BD, NT, double, double, false>(P, slots, st);
     if (prec == 1) return sid ? launch_one<BD, NT, float, float, true>(P, slots, st)
@@ -786,6 +1030,8 @@ bool supported_bdim(int bd) { return bd == 1 || bd == 4 || bd == 9; }
 size_t solver_lds_bytes(int K, int nt) { return lds_bytes(K, nt); }
 
 int64_t solver_slot_bytes(int K, int64_t Mp, int prec) { return slot_bytes_for(K, Mp, prec != 0); }
+
+int64_t solver_slot_bytes_proj(int K, int64_t Mp, int64_t nIp) { return slot_bytes_proj(K, Mp, nIp); }
 
 hipError_t launch_solver(const KParams& P, int bd, int prec, bool sid, int nt, int slots, hipStream_t st) {
     switch (bd) {

@@ -11,7 +11,9 @@ bool supported_bdim(int bd);
 size_t solver_lds_bytes(int K, int nt);
 // Working memory of one resident workgroup (bytes) for K shifts and Mp rows.
 int64_t solver_slot_bytes(int K, int64_t Mp, int prec);
-// prec: 0 FP64, 1 FP32, 2 FP32 compute with bfloat16 blocks; sid: S = I.
+// Same for the projected (requested-rows-only) FP64 solve with nIp padded rows.
+int64_t solver_slot_bytes_proj(int K, int64_t Mp, int64_t nIp);
+// prec: 0 FP64, 1 FP32, 2 FP32 compute with bfloat16 blocks, 3 projected FP64; sid: S = I.
 hipError_t launch_solver(const KParams& P, int bd, int prec, bool sid, int nt, int slots, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 

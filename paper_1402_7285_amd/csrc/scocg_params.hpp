@@ -57,6 +57,7 @@ struct KParams {
     char* ws;
     int64_t slot_bytes;
     int64_t Mp;                // padded max cluster dimension (elements)
+    int64_t nIp;               // projected mode: padded max requested rows
     // outputs (device)
     double* out;               // interleaved complex
     int32_t* iters;

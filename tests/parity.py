@@ -29,8 +29,9 @@ def inv_norm(Hc, Sc, z):
 
 
 def compare_rhs(xg, itg, stg, res, Hc, Sc, shifts, b, tol, rtol=1e-8, slack=2.0, report=None,
-                max_shift=3, iter_frac=0.08, tag=""):
-    """xg: [K, M] GPU x; res: oracle ScocgResult with x [M, K].  Returns worst rel err."""
+                max_shift=3, iter_frac=0.08, tag="", rows=None):
+    """xg: [K, n] GPU x (or its ``rows``); res: oracle ScocgResult with x [n, K].
+    Returns the worst relative error."""
     K = shifts.size
     worst = 0.0
     errs = []
@@ -53,6 +54,8 @@ def compare_rhs(xg, itg, stg, res, Hc, Sc, shifts, b, tol, rtol=1e-8, slack=2.0,
             errs.append(f"{tag} shift {k}: rel err {rel:.3e} > {rtol:.1e} (iters {itg[k]})")
             continue
         xs = dense_solve(Hc, Sc, shifts[k], b)
+        if rows is not None:
+            xs = xs[rows]
         bound = inv_norm(Hc, Sc, shifts[k]) * slack * tol * np.linalg.norm(b)
         eg, eo = np.linalg.norm(xg[k] - xs), np.linalg.norm(xo - xs)
         if not (eg <= bound and eo <= bound):

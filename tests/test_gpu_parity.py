@@ -7,7 +7,7 @@ multiples of the workgroup size).
 import numpy as np
 import pytest
 
-from oracle import CONVERGED, MAXITER, local_system, scocg
+from oracle import CONVERGED, MAXITER, local_system, scocg, scocg_projected
 from synth import bsr_to_scipy, make_config, make_problem
 from tests.parity import compare_rhs
 
@@ -27,11 +27,15 @@ def _check_problem(B, prob, rtol=1e-8, oracle_kw=None, **opt):
     print(f"[parity] {prob.name} M={prob.M} K={prob.nshift} nrhs={prob.nrhs} opt={opt}", flush=True)
     P, plan = _plan(B, prob, full_x=True, **opt)
     r = plan.solve()
-    Pg, plang = _plan(B, prob, full_x=False, **opt)
+    Pg, plang = _plan(B, prob, full_x=False, projected=0, **opt)
     rg = plang.solve()
+    Pp, planp = _plan(B, prob, full_x=False, **opt)
+    assert planp.info["global"] & 2, "SELECTED_G in FP64 runs the projected solve by default"
+    rp = planp.solve()
     Hcsr = bsr_to_scipy(prob.H)
     Scsr = bsr_to_scipy(prob.S) if prob.S is not None else None
     worst, report = 0.0, []
+    worst_p, report_p = [0.0], []
     okw = dict(oracle_kw or {})
     if "seed_index" in opt and opt["seed_index"] >= 0:
         okw["seed"] = opt["seed_index"]
@@ -44,9 +48,18 @@ def _check_problem(B, prob, rtol=1e-8, oracle_kw=None, **opt):
         assert xg.shape == (prob.nshift, orb.size)
         worst = max(worst, compare_rhs(xg, r["iters"][j], r["status"][j], res, Hc, Sc, prob.shifts, b,
                                        opt.get("tol", prob.tol), rtol=rtol, report=report, tag=f"rhs {j}"))
-        # selected rows equal the full-x rows bit for bit
+        # selected rows of the full solve equal the full-x rows bit for bit
         pos = np.searchsorted(orb, prob.outs(j))
         assert np.array_equal(rg["G"][j], xg[:, pos])
+        # the projected solve against the projected (three-term) oracle
+        resp = scocg_projected(Hc, Sc, prob.shifts, b, pos, opt.get("tol", prob.tol), **okw)
+        worst_p[0] = max(worst_p[0], compare_rhs(rp["G"][j], rp["iters"][j], rp["status"][j], resp, Hc, Sc,
+                                                 prob.shifts, b, opt.get("tol", prob.tol), rtol=rtol,
+                                                 report=report_p, tag=f"proj rhs {j}", rows=pos,
+                                                 iter_frac=0.25))
+        # the three-term form's counts are more rounding-sensitive: two CPU runs
+        # differing only in matvec summation order spread by up to ~16%
+        assert abs(int(rp["stats"][j][0]) - resp.n_outer) <= max(3, 0.25 * resp.n_outer)
         st = r["stats"][j]
         assert abs(int(st[0]) - res.n_outer) <= max(3, 0.08 * res.n_outer), \
             f"RHS {j}: outer iterations gpu {st[0]} oracle {res.n_outer}"
@@ -54,6 +67,7 @@ def _check_problem(B, prob, rtol=1e-8, oracle_kw=None, **opt):
     print(f"[parity] worst rel err {worst:.2e}; shifts with other iteration counts "
           f"(tag, k, gpu, oracle, rel): {report[:12]}{' ...' if len(report) > 12 else ''} ({len(report)})",
           flush=True)
+    print(f"[parity] projected: worst rel err {worst_p[0]:.2e}; shifts with other counts {len(report_p)}", flush=True)
     return r
 
 

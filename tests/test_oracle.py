@@ -399,3 +399,28 @@ def test_projected_diagonal_and_2x2():
     det = (z2 - h11) * (z2 - h22) - h12 ** 2
     assert np.allclose(r2.x[0], (z2 - h22) / det, rtol=1e-12)
     assert np.allclose(r2.x[1], h12 / det, rtol=1e-12)
+
+
+def test_projected_count_spread_between_cpu_variants(cfg0):
+    """The three-term form's iteration counts move more under rounding than the
+    two-term form's (the GPU parity allowance for it, 25%, is set above this
+    spread), while the converged rows still agree to ~1e-10."""
+    p, H = cfg0
+
+    class DenseOp:
+        def __init__(self, A):
+            self.A = A
+
+        def __matmul__(self, v):
+            return self.A @ v
+
+    D = DenseOp(H.toarray())
+    spread, worst = 0.0, 0.0
+    for j in range(3):
+        b = _unit(p.M, int(p.rhs[j]))
+        rows = p.outs(j)
+        a = scocg_projected(H, None, p.shifts, b, rows, p.tol)
+        c = scocg_projected(D, None, p.shifts, b, rows, p.tol)
+        spread = max(spread, float((np.abs(a.iters - c.iters) / a.iters).max()))
+        worst = max(worst, float((np.linalg.norm(a.x - c.x, axis=0) / np.linalg.norm(a.x, axis=0)).max()))
+    assert spread < 0.25 and worst < 1e-9
