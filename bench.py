@@ -160,6 +160,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--projected", type=int, default=1, help="FP64 SELECTED_G: rows-only solve (default 1)")
     ap.add_argument("--copy-calib", type=int, default=0, help="only run a device copy of this many bytes")
+    ap.add_argument("--maxiter", type=int, default=0,
+                    help="diagnostics only: cap outer iterations (changes the workload; not a metric run)")
     args = ap.parse_args()
     if args.copy_calib:
         copy_calibration(args.copy_calib)
@@ -184,7 +186,7 @@ def main():
     if prob.cluster_ptr is not None:
         kw.update(cluster_ptr=prob.cluster_ptr, cluster_atoms=prob.cluster_atoms)
     plan = B.Plan(P, prob.shifts, prob.rhs, tol=args.tol, precision=PREC[args.precision], audit=1,
-                  threads=args.threads, slots=args.slots, projected=args.projected, **kw)
+                  threads=args.threads, slots=args.slots, projected=args.projected, maxiter=args.maxiter, **kw)
     projected = bool(plan.info["global"] & 2)
     bufs = plan.alloc_outputs()
     stream = torch.cuda.current_stream()

@@ -230,6 +230,30 @@ scocg_status scocg_plan_run(scocg_plan* plan, void* stream, scocg_z* out, int32_
                             int8_t* status, double* resid);
 
 /*
+ * Records the whole run (queue reset and the persistent solver) on `stream`
+ * (a non-default hipStream_t) into a HIP graph bound to these output
+ * buffers, and instantiates it; scocg_plan_replay launches it again.  The
+ * graph holds no memset nodes.  Replays on one plan must not overlap.
+ */
+scocg_status scocg_plan_capture(scocg_plan* plan, void* stream, scocg_z* out, int32_t* iters,
+                                int8_t* status, double* resid);
+scocg_status scocg_plan_replay(scocg_plan* plan, void* stream);
+
+/*
+ * Autotuner: times one probe solve (every RHS capped at probe_iters outer
+ * iterations, after a warm-up) for each workgroup size in {256, 512, 1024}
+ * and each count of resident workgroups per compute unit in {1, 2}, and
+ * returns the fastest pair (threads, total resident workgroups) and its
+ * probe time in seconds.  The arguments are those of scocg_plan_create; the
+ * caller caches the answer (the Python binding keys a JSON file by GPU
+ * architecture and problem shape).
+ */
+scocg_status scocg_autotune(scocg_problem* P, const scocg_options* opt, int32_t nshift,
+                            const scocg_z* shifts, int32_t nrhs, const int32_t* rhs_index,
+                            const scocg_rhs_spec* spec, int32_t probe_iters, int32_t* best_threads,
+                            int32_t* best_slots, double* best_seconds);
+
+/*
  * Per-RHS counters of the last run, copied to host int64[nrhs * SCOCG_NSTAT]
  * (synchronises the run's stream):
  *   [0] outer iterations   [1] sum over iterations of shifts updated

@@ -29,7 +29,8 @@ EXPORTS = (
     "scocg_last_error", "scocg_version", "scocg_matrix_from_bsr", "scocg_matrix_from_csr",
     "scocg_matrix_free", "scocg_problem_create", "scocg_problem_free", "scocg_options_default",
     "scocg_plan_create", "scocg_plan_free", "scocg_plan_out_count", "scocg_plan_out_offsets", "scocg_plan_info",
-    "scocg_plan_run", "scocg_plan_stats", "scocg_solve",
+    "scocg_plan_run", "scocg_plan_stats", "scocg_solve", "scocg_plan_capture", "scocg_plan_replay",
+    "scocg_autotune",
 )
 
 
@@ -78,6 +79,10 @@ def _declare(lib):
         "scocg_plan_info": (st, [_VP, _VP]),
         "scocg_plan_run": (st, [_VP, _VP, _VP, _VP, _VP, _VP]),
         "scocg_plan_stats": (st, [_VP, _VP]),
+        "scocg_plan_capture": (st, [_VP, _VP, _VP, _VP, _VP, _VP]),
+        "scocg_plan_replay": (st, [_VP, _VP]),
+        "scocg_autotune": (st, [_VP, C.POINTER(scocg_options), i32, _VP, i32, _VP, C.POINTER(scocg_rhs_spec),
+                                i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_double)]),
         "scocg_solve": (st, [_VP, C.POINTER(scocg_options), i32, _VP, i32, _VP,
                              C.POINTER(scocg_rhs_spec), _VP, _VP, _VP, _VP]),
     }
@@ -221,6 +226,24 @@ def scocg_plan_run(h, stream, out, iters=None, status=None, resid=None):
     return _check(load().scocg_plan_run(h, sp, _tptr(out), _tptr(iters), _tptr(status), _tptr(resid)))
 
 
+def scocg_plan_capture(h, stream, out, iters=None, status=None, resid=None):
+    return _check(load().scocg_plan_capture(h, C.c_void_p(stream.cuda_stream), _tptr(out), _tptr(iters),
+                                            _tptr(status), _tptr(resid)))
+
+
+def scocg_plan_replay(h, stream):
+    return _check(load().scocg_plan_replay(h, C.c_void_p(stream.cuda_stream)))
+
+
+def scocg_autotune(problem, opt, shifts, rhs_index, spec: "_Spec", probe_iters):
+    z, zp = _shifts(shifts)
+    rhs = np.ascontiguousarray(rhs_index, dtype=np.int32)
+    t, sl, sec = C.c_int32(0), C.c_int32(0), C.c_double(0.0)
+    _check(load().scocg_autotune(problem, C.byref(opt), int(z.size), zp, int(rhs.size), _ptr(rhs),
+                                 C.byref(spec.struct), int(probe_iters), C.byref(t), C.byref(sl), C.byref(sec)))
+    return int(t.value), int(sl.value), float(sec.value)
+
+
 def scocg_plan_stats(h, nrhs) -> np.ndarray:
     st = np.zeros((nrhs, NSTAT), dtype=np.int64)
     _check(load().scocg_plan_stats(h, _ptr(st)))
@@ -310,6 +333,13 @@ class Plan:
     def stats(self) -> np.ndarray:
         return scocg_plan_stats(self.h, self.nrhs)
 
+    def capture(self, bufs, stream):
+        """Record the run into a HIP graph bound to ``bufs`` on ``stream`` (non-default)."""
+        return scocg_plan_capture(self.h, stream, bufs["out"], bufs["iters"], bufs["status"], bufs["resid"])
+
+    def replay(self, stream):
+        return scocg_plan_replay(self.h, stream)
+
     def solve(self):
         """Run once and return host results: dict(G=list of [K, nout] arrays, iters, status, resid)."""
         import torch
@@ -328,3 +358,32 @@ class Plan:
         if getattr(self, "h", None) and _LIB is not None:
             scocg_plan_free(self.h)
             self.h = None
+
+
+def autotune(problem: Problem, shifts, rhs, probe_iters=200, cache_path=None, key_extra="", **plan_kwargs):
+    """Pick (threads, slots) for this problem shape by timing short probe solves
+    on the device; results are cached in a JSON file keyed by the GPU
+    architecture and the problem shape."""
+    import json
+    import torch
+    opts = {k: v for k, v in plan_kwargs.items() if hasattr(scocg_options, k)}
+    spec_kw = {k: v for k, v in plan_kwargs.items() if not hasattr(scocg_options, k)}
+    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName
+    shifts = np.asarray(shifts, dtype=np.complex128)
+    rhs = np.asarray(rhs, dtype=np.int32)
+    key = f"{arch}|K{shifts.size}|R{rhs.size}|{sorted(opts.items())}|{key_extra}"
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+        if key in cache:
+            return cache[key]
+    opt = scocg_options_default(**opts)
+    spec = make_spec(**spec_kw)
+    t, sl, sec = scocg_autotune(problem.h, opt, shifts, rhs, spec, probe_iters)
+    res = {"threads": t, "slots": sl, "probe_seconds": sec, "probe_iters": probe_iters}
+    if cache_path:
+        cache[key] = res
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return res

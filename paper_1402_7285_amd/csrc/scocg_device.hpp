@@ -45,6 +45,10 @@ template <class T> __device__ __forceinline__ zc ld(const v2<T>* p, int64_t i) {
     v2<T> v = p[i];
     return zc{(double)v.x, (double)v.y};
 }
+// The value a complex number takes once stored in precision T (no memory trip).
+template <class T> __device__ __forceinline__ zc rnd(zc a) {
+    return zc{(double)(T)a.re, (double)(T)a.im};
+}
 template <class T> __device__ __forceinline__ void st(v2<T>* p, int64_t i, zc a) {
     v2<T> v;
     v.x = (T)a.re;

@@ -126,6 +126,8 @@ struct scocg_plan {
     int64_t* dstats = nullptr;
     bool global = true;
     hipStream_t last_stream = nullptr;
+    hipGraph_t graph = nullptr;          // captured run (scocg_plan_capture)
+    hipGraphExec_t gexec = nullptr;
 };
 
 // ---------------------------------------------------------------------------
@@ -401,6 +403,8 @@ extern "C" void scocg_plan_free(scocg_plan* pl) {
     (void)hipSetDevice(pl->P->device);
     if (pl->last_stream) (void)hipStreamSynchronize(pl->last_stream);
     else (void)hipDeviceSynchronize();
+    if (pl->gexec) (void)hipGraphExecDestroy(pl->gexec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
     dev_free(pl->dz);
     dev_free(pl->dsys);
     dev_free(pl->drhs);
@@ -848,4 +852,106 @@ extern "C" scocg_status scocg_solve(scocg_problem* P, const scocg_options* opt, 
     }
     cleanup();
     return st;
+}
+
+// ---------------------------------------------------------------------------
+// graph capture / replay
+// ---------------------------------------------------------------------------
+extern "C" scocg_status scocg_plan_capture(scocg_plan* pl, void* stream, scocg_z* out, int32_t* iters,
+                                           int8_t* status, double* resid) {
+    if (!pl) return fail(SCOCG_E_ARG, "plan is NULL");
+    if (!stream) return fail(SCOCG_E_ARG, "capture needs a non-default stream");
+    HIP_TRY(hipSetDevice(pl->P->device));
+    if (pl->gexec) { (void)hipGraphExecDestroy(pl->gexec); pl->gexec = nullptr; }
+    if (pl->graph) { (void)hipGraphDestroy(pl->graph); pl->graph = nullptr; }
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const scocg_status rs = scocg_plan_run(pl, stream, out, iters, status, resid);
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(st, &g);
+    if (rs != SCOCG_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rs;
+    }
+    if (ee != hipSuccess) return fail(SCOCG_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ee));
+    pl->graph = g;
+    HIP_TRY(hipGraphInstantiate(&pl->gexec, pl->graph, nullptr, nullptr, 0));
+    return SCOCG_OK;
+}
+
+extern "C" scocg_status scocg_plan_replay(scocg_plan* pl, void* stream) {
+    if (!pl) return fail(SCOCG_E_ARG, "plan is NULL");
+    if (!pl->gexec) return fail(SCOCG_E_ARG, "no captured graph: call scocg_plan_capture first");
+    HIP_TRY(hipSetDevice(pl->P->device));
+    pl->last_stream = (hipStream_t)stream;
+    HIP_TRY(hipGraphLaunch(pl->gexec, (hipStream_t)stream));
+    return SCOCG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: workgroup size x resident workgroups per CU
+// ---------------------------------------------------------------------------
+extern "C" scocg_status scocg_autotune(scocg_problem* P, const scocg_options* opt_in, int32_t nshift,
+                                       const scocg_z* shifts, int32_t nrhs, const int32_t* rhs_index,
+                                       const scocg_rhs_spec* spec, int32_t probe_iters, int32_t* best_threads,
+                                       int32_t* best_slots, double* best_seconds) {
+    if (!P || !best_threads || !best_slots) return fail(SCOCG_E_ARG, "NULL argument");
+    if (probe_iters <= 0) return fail(SCOCG_E_ARG, "probe_iters must be > 0");
+    scocg_options opt;
+    if (opt_in) opt = *opt_in; else scocg_options_default(&opt);
+    HIP_TRY(hipSetDevice(P->device));
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess || cus <= 0)
+        cus = 256;
+    hipStream_t st = nullptr;
+    HIP_TRY(hipStreamCreate(&st));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    double best = 1e300;
+    int bt = 0, bs = 0;
+    scocg_status result = SCOCG_OK;
+    const int threads_c[3] = {256, 512, 1024};
+    for (int ti = 0; ti < 3 && result == SCOCG_OK; ++ti) {
+        for (int per_cu = 1; per_cu <= 2 && result == SCOCG_OK; ++per_cu) {
+            scocg_options o = opt;
+            o.maxiter = probe_iters;
+            o.threads = threads_c[ti];
+            o.slots = std::max(1, std::min(nrhs, cus * per_cu));
+            scocg_plan* pl = nullptr;
+            scocg_status s2 = scocg_plan_create(P, &o, nshift, shifts, nrhs, rhs_index, spec, &pl);
+            if (s2 < 0) { result = s2; break; }
+            if (pl->slots != o.slots) { scocg_plan_free(pl); continue; }   // memory-capped duplicate
+            const size_t nk = (size_t)std::max(1, nrhs) * nshift;
+            scocg_z* dout = nullptr;
+            if (hipMalloc((void**)&dout, sizeof(scocg_z) * std::max<int64_t>(1, pl->out_count)) != hipSuccess) {
+                scocg_plan_free(pl);
+                result = fail(SCOCG_E_NOMEM, "autotune output buffer");
+                break;
+            }
+            (void)nk;
+            float ms = 0.f;
+            hipError_t he = hipSuccess;
+            if ((s2 = scocg_plan_run(pl, st, dout, nullptr, nullptr, nullptr)) == SCOCG_OK &&   // warm-up
+                (he = hipStreamSynchronize(st)) == hipSuccess &&
+                (he = hipEventRecord(e0, st)) == hipSuccess &&
+                (s2 = scocg_plan_run(pl, st, dout, nullptr, nullptr, nullptr)) == SCOCG_OK &&
+                (he = hipEventRecord(e1, st)) == hipSuccess && (he = hipEventSynchronize(e1)) == hipSuccess &&
+                (he = hipEventElapsedTime(&ms, e0, e1)) == hipSuccess) {
+                if (ms < best) { best = ms; bt = o.threads; bs = o.slots; }
+            }
+            dev_free(dout);
+            scocg_plan_free(pl);
+            if (s2 != SCOCG_OK) { result = s2; break; }
+            if (he != hipSuccess) { result = fail(SCOCG_E_DEVICE, "autotune: %s", hipGetErrorString(he)); break; }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(st);
+    if (result != SCOCG_OK) return result;
+    *best_threads = bt;
+    *best_slots = bs;
+    if (best_seconds) *best_seconds = best / 1e3;
+    return SCOCG_OK;
 }

@@ -92,6 +92,7 @@ template <int BD, int NT, class TV, class TB, bool SID>
 __device__ __forceinline__ zc op_apply(const TB* __restrict__ H, const TB* __restrict__ S, const Sys& sy, zc z,
                                        const v2<TV>* __restrict__ p, v2<TV>* __restrict__ q) {
     zc mu = zmk(0.0, 0.0);
+#pragma unroll 4
     for (int i = threadIdx.x; i < sy.M; i += NT) {
         const int a = i / BD, r = i - a * BD;
         const int64_t e0 = sy.rowptr[a], e1 = sy.rowptr[a + 1];
@@ -125,9 +126,8 @@ __device__ __forceinline__ zc op_apply(const TB* __restrict__ H, const TB* __res
         }
         const zc pi_ = ld<TV>(p, i);
         const zc sp = SID ? pi_ : zmk((double)sr, (double)si);
-        zc qv = zsub(zmul(z, sp), zmk((double)hr, (double)hi));
-        st<TV>(q, i, qv);
-        qv = ld<TV>(q, i);   // the stored (possibly rounded) value enters p^T q
+        const zc qv = rnd<TV>(zsub(zmul(z, sp), zmk((double)hr, (double)hi)));
+        st<TV>(q, i, qv);    // the stored (possibly rounded) value enters p^T q
         mu = zadd(mu, zmul(pi_, qv));
     }
     return mu;
@@ -138,6 +138,7 @@ template <int BD, int NT, class TV, class TB>
 __device__ __forceinline__ double spmv_S(const TB* __restrict__ S, const Sys& sy, const v2<TV>* __restrict__ d,
                                          v2<TV>* __restrict__ w) {
     double part = 0.0;
+#pragma unroll 4
     for (int i = threadIdx.x; i < sy.M; i += NT) {
         const int a = i / BD, r = i - a * BD;
         const int64_t e0 = sy.rowptr[a], e1 = sy.rowptr[a + 1];
@@ -155,9 +156,8 @@ __device__ __forceinline__ double spmv_S(const TB* __restrict__ S, const Sys& sy
                 si += s * dv.y;
             }
         }
-        const zc wv = zmk((double)sr, (double)si);
-        st<TV>(w, i, wv);
-        const zc ws = ld<TV>(w, i);
+        const zc ws = rnd<TV>(zmk((double)sr, (double)si));
+        st<TV>(w, i, ws);
         const zc dv = ld<TV>(d, i);
         part += dv.re * ws.re + dv.im * ws.im;
     }
@@ -169,6 +169,7 @@ __device__ __forceinline__ double spmv_S(const TB* __restrict__ S, const Sys& sy
 template <int BD, int NT, class TV, class TB>
 __device__ int inner_cg(const TB* S, const Sys& sy, const v2<TV>* rho, v2<TV>* r, v2<TV>* res,
                         v2<TV>* d, v2<TV>* w, double nr2, double tol, int maxit, double* red) {
+#pragma unroll 4
     for (int i = threadIdx.x; i < sy.M; i += NT) {
         const zc v = ld<TV>(rho, i);
         st<TV>(r, i, zmk(0.0, 0.0));
@@ -185,18 +186,19 @@ __device__ int inner_cg(const TB* S, const Sys& sy, const v2<TV>* rho, v2<TV>* r
         block_sum<NT, 1>(dw, red);
         const double a = rr / dw[0];
         double rn[1] = {0.0};
+#pragma unroll 4
         for (int i = threadIdx.x; i < sy.M; i += NT) {
             const zc dv = ld<TV>(d, i), wv = ld<TV>(w, i);
             zc rv = ld<TV>(r, i), sv = ld<TV>(res, i);
             rv = zmk(rv.re + a * dv.re, rv.im + a * dv.im);
-            sv = zmk(sv.re - a * wv.re, sv.im - a * wv.im);
+            sv = rnd<TV>(zmk(sv.re - a * wv.re, sv.im - a * wv.im));
             st<TV>(r, i, rv);
             st<TV>(res, i, sv);
-            const zc s2 = ld<TV>(res, i);
-            rn[0] += s2.re * s2.re + s2.im * s2.im;
+            rn[0] += sv.re * sv.re + sv.im * sv.im;
         }
         block_sum<NT, 1>(rn, red);
         const double bt = rn[0] / rr;
+#pragma unroll 4
         for (int i = threadIdx.x; i < sy.M; i += NT) {
             const zc sv = ld<TV>(res, i), dv = ld<TV>(d, i);
             st<TV>(d, i, zmk(sv.re + bt * dv.re, sv.im + bt * dv.im));
@@ -351,6 +353,7 @@ __device__ double true_residual(const KParams& P, const Sys& sy, zc z, const dou
     __syncthreads();
     (void)op_apply<BD, NT, double, double, SID>(P.Hv64, P.Sv64, sy, z, x, q);
     double nn[1] = {0.0};
+#pragma unroll 4
     for (int i = threadIdx.x; i < sy.M; i += NT) {
         const zc qv = ld<double>(q, i);
         const zc v = zmk((i == bl ? 1.0 : 0.0) - qv.re, -qv.im);
@@ -537,8 +540,8 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
         // ---- rho -= alpha q;  nu^2 = ||rho||^2
         double nn[1] = {0.0};
         for (int i = tid; i < M; i += NT) {
-            st<TV>(rho, i, zsub(ld<TV>(rho, i), zmul(alpha, ld<TV>(q, i))));
-            const zc b = ld<TV>(rho, i);
+            const zc b = rnd<TV>(zsub(ld<TV>(rho, i), zmul(alpha, ld<TV>(q, i))));
+            st<TV>(rho, i, b);
             nn[0] += b.re * b.re + b.im * b.im;
         }
         block_sum<NT, 1>(nn, L.red);
