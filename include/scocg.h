@@ -253,6 +253,42 @@ scocg_status scocg_autotune(scocg_problem* P, const scocg_options* opt, int32_t 
                             const scocg_rhs_spec* spec, int32_t probe_iters, int32_t* best_threads,
                             int32_t* best_slots, double* best_seconds);
 
+/* ---- learned RHS-cost predictor (for the work-queue order) ----------------- */
+/*
+ * 16 local-environment features of every RHS orbital j of a plan, computed
+ * on the device from its cluster map and the FP64 blocks; device float
+ * [nrhs][16], asynchronous on `stream`:
+ *   0 cluster atoms n_j          1 block entries / n_j      2 neighbours of c(j)
+ *   3 entries in the neighbours' rows                       4-6 orbital s / p / d
+ *   7 H_jj                        8 ||H_cc||_F               9-10 Gershgorin
+ *   bounds of the on-site block   11-13 mean / max / std of ||H_cb||_F over
+ *   neighbours b                  14 sum_{i != j} |H_ji|     15 mean ||S_cb||_F
+ */
+scocg_status scocg_features(scocg_plan* plan, float* feats, void* stream);
+
+/* Number of MLP parameters (5313): W1[64][16], b1[64], W2[64][64], b2[64], W3[64], b3. */
+int64_t scocg_mlp_nparams(void);
+/* Floats of the device work buffer a training step needs. */
+int64_t scocg_mlp_work_floats(void);
+
+/*
+ * y[s] = MLP(x[s]) for s < n: 16 -> 64 -> 64 -> 1 with ReLU, FP32; all
+ * device pointers (w float[5313], x float[n][16], y float[n]).
+ */
+scocg_status scocg_mlp_forward(const float* w, const float* x, int64_t n, float* y, void* stream);
+
+/*
+ * One training step on the batch idx[0..m) of (x, t) (idx NULL: samples
+ * 0..m-1): loss = mean (y - t)^2 over the batch (device float scalar, may be
+ * NULL), gradient (device float[5313], may be NULL), and, if lr > 0, one Adam
+ * step (beta 0.9 / 0.999, eps 1e-8, bias-corrected with step >= 1) on w with
+ * moments adam_m, adam_v.  work: device float[scocg_mlp_work_floats()].
+ * Deterministic: per-wave partial gradients summed in a fixed order in FP64.
+ */
+scocg_status scocg_mlp_train_step(float* w, float* adam_m, float* adam_v, const float* x, const float* t,
+                                  const int32_t* idx, int64_t m, float lr, int32_t step, float* loss,
+                                  float* grad, float* work, void* stream);
+
 /*
  * Per-RHS counters of the last run, copied to host int64[nrhs * SCOCG_NSTAT]
  * (synchronises the run's stream):

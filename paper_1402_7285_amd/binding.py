@@ -30,7 +30,8 @@ EXPORTS = (
     "scocg_matrix_free", "scocg_problem_create", "scocg_problem_free", "scocg_options_default",
     "scocg_plan_create", "scocg_plan_free", "scocg_plan_out_count", "scocg_plan_out_offsets", "scocg_plan_info",
     "scocg_plan_run", "scocg_plan_stats", "scocg_solve", "scocg_plan_capture", "scocg_plan_replay",
-    "scocg_autotune",
+    "scocg_autotune", "scocg_features", "scocg_mlp_nparams", "scocg_mlp_work_floats", "scocg_mlp_forward",
+    "scocg_mlp_train_step",
 )
 
 
@@ -81,6 +82,11 @@ def _declare(lib):
         "scocg_plan_stats": (st, [_VP, _VP]),
         "scocg_plan_capture": (st, [_VP, _VP, _VP, _VP, _VP, _VP]),
         "scocg_plan_replay": (st, [_VP, _VP]),
+        "scocg_features": (st, [_VP, _VP, _VP]),
+        "scocg_mlp_nparams": (i64, []),
+        "scocg_mlp_work_floats": (i64, []),
+        "scocg_mlp_forward": (st, [_VP, _VP, i64, _VP, _VP]),
+        "scocg_mlp_train_step": (st, [_VP, _VP, _VP, _VP, _VP, _VP, i64, C.c_float, i32, _VP, _VP, _VP, _VP]),
         "scocg_autotune": (st, [_VP, C.POINTER(scocg_options), i32, _VP, i32, _VP, C.POINTER(scocg_rhs_spec),
                                 i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_double)]),
         "scocg_solve": (st, [_VP, C.POINTER(scocg_options), i32, _VP, i32, _VP,
@@ -244,6 +250,33 @@ def scocg_autotune(problem, opt, shifts, rhs_index, spec: "_Spec", probe_iters):
     return int(t.value), int(sl.value), float(sec.value)
 
 
+def _sp(stream):
+    return None if stream is None else C.c_void_p(stream.cuda_stream)
+
+
+def scocg_features(h, feats, stream=None):
+    return _check(load().scocg_features(h, _tptr(feats), _sp(stream)))
+
+
+def scocg_mlp_nparams() -> int:
+    return int(load().scocg_mlp_nparams())
+
+
+def scocg_mlp_work_floats() -> int:
+    return int(load().scocg_mlp_work_floats())
+
+
+def scocg_mlp_forward(w, x, y, stream=None):
+    return _check(load().scocg_mlp_forward(_tptr(w), _tptr(x), int(x.shape[0]), _tptr(y), _sp(stream)))
+
+
+def scocg_mlp_train_step(w, m, v, x, t, idx, lr, step, loss, grad, work, stream=None):
+    n = int(idx.shape[0]) if idx is not None else int(x.shape[0])
+    return _check(load().scocg_mlp_train_step(_tptr(w), _tptr(m), _tptr(v), _tptr(x), _tptr(t), _tptr(idx), n,
+                                              float(lr), int(step), _tptr(loss), _tptr(grad), _tptr(work),
+                                              _sp(stream)))
+
+
 def scocg_plan_stats(h, nrhs) -> np.ndarray:
     st = np.zeros((nrhs, NSTAT), dtype=np.int64)
     _check(load().scocg_plan_stats(h, _ptr(st)))
@@ -332,6 +365,13 @@ class Plan:
 
     def stats(self) -> np.ndarray:
         return scocg_plan_stats(self.h, self.nrhs)
+
+    def features(self):
+        """[nrhs, 16] FP32 features computed on the device (torch tensor)."""
+        import torch
+        f = torch.empty((max(1, self.nrhs), 16), dtype=torch.float32, device="cuda")
+        scocg_features(self.h, f, torch.cuda.current_stream())
+        return f[: self.nrhs]
 
     def capture(self, bufs, stream):
         """Record the run into a HIP graph bound to ``bufs`` on ``stream`` (non-default)."""

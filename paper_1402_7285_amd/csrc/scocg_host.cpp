@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/scocg.h"
+#include "mlp_params.hpp"
 #include "scocg_launch.hpp"
 #include "scocg_params.hpp"
 
@@ -733,14 +734,7 @@ extern "C" scocg_status scocg_plan_out_offsets(const scocg_plan* pl, int64_t* of
     return SCOCG_OK;
 }
 
-extern "C" scocg_status scocg_plan_run(scocg_plan* pl, void* stream, scocg_z* out, int32_t* iters,
-                                       int8_t* status, double* resid) {
-    if (!pl) return fail(SCOCG_E_ARG, "plan is NULL");
-    if (!out && pl->out_count > 0) return fail(SCOCG_E_ARG, "out is NULL");
-    if (pl->nrhs == 0) return SCOCG_OK;
-    HIP_TRY(hipSetDevice(pl->P->device));
-    hipStream_t st = (hipStream_t)stream;
-    pl->last_stream = st;
+static KParams make_kparams(const scocg_plan* pl, scocg_z* out, int32_t* iters, int8_t* status, double* resid) {
     const scocg_problem* P = pl->P;
     KParams k{};
     if (pl->prec == SCOCG_FP64) {
@@ -785,6 +779,19 @@ extern "C" scocg_status scocg_plan_run(scocg_plan* pl, void* stream, scocg_z* ou
     k.status = status;
     k.resid = resid;
     k.stats = pl->dstats;
+    return k;
+}
+
+extern "C" scocg_status scocg_plan_run(scocg_plan* pl, void* stream, scocg_z* out, int32_t* iters,
+                                       int8_t* status, double* resid) {
+    if (!pl) return fail(SCOCG_E_ARG, "plan is NULL");
+    if (!out && pl->out_count > 0) return fail(SCOCG_E_ARG, "out is NULL");
+    if (pl->nrhs == 0) return SCOCG_OK;
+    HIP_TRY(hipSetDevice(pl->P->device));
+    hipStream_t st = (hipStream_t)stream;
+    pl->last_stream = st;
+    const scocg_problem* P = pl->P;
+    KParams k = make_kparams(pl, out, iters, status, resid);
     (void)hipGetLastError();   // drop any error another caller left on this thread
     HIP_TRY(scocg::launch_fill_i32(pl->dqueue, 0, 1, st));
     HIP_TRY(scocg::launch_solver(k, P->bd, pl->proj ? 3 : pl->prec, !P->has_S, pl->nt, pl->slots, st));
@@ -953,5 +960,49 @@ extern "C" scocg_status scocg_autotune(scocg_problem* P, const scocg_options* op
     *best_threads = bt;
     *best_slots = bs;
     if (best_seconds) *best_seconds = best / 1e3;
+    return SCOCG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// learned RHS-cost predictor: features, MLP forward, training step
+// ---------------------------------------------------------------------------
+extern "C" int64_t scocg_mlp_nparams(void) { return scocg::NPARAM; }
+
+extern "C" int64_t scocg_mlp_work_floats(void) {
+    return (int64_t)scocg::GRAD_BLOCKS * 4 * (scocg::NPARAM + 1);
+}
+
+extern "C" scocg_status scocg_features(scocg_plan* pl, float* feats, void* stream) {
+    if (!pl) return fail(SCOCG_E_ARG, "plan is NULL");
+    if (pl->nrhs == 0) return SCOCG_OK;
+    if (!feats) return fail(SCOCG_E_ARG, "feats is NULL");
+    HIP_TRY(hipSetDevice(pl->P->device));
+    const KParams k = make_kparams(pl, nullptr, nullptr, nullptr, nullptr);
+    (void)hipGetLastError();
+    HIP_TRY(scocg::launch_features(k, pl->P->bd, pl->P->has_S ? 1 : 0, feats, (hipStream_t)stream));
+    return SCOCG_OK;
+}
+
+extern "C" scocg_status scocg_mlp_forward(const float* w, const float* x, int64_t n, float* y, void* stream) {
+    if (n < 0) return fail(SCOCG_E_ARG, "n < 0");
+    if (n == 0) return SCOCG_OK;
+    if (!w || !x || !y) return fail(SCOCG_E_ARG, "NULL argument");
+    (void)hipGetLastError();
+    HIP_TRY(scocg::launch_mlp_forward(w, x, n, y, (hipStream_t)stream));
+    return SCOCG_OK;
+}
+
+extern "C" scocg_status scocg_mlp_train_step(float* w, float* adam_m, float* adam_v, const float* x, const float* t,
+                                             const int32_t* idx, int64_t m, float lr, int32_t step, float* loss,
+                                             float* grad, float* work, void* stream) {
+    if (!w || !x || !t || !work || m <= 0) return fail(SCOCG_E_ARG, "bad argument");
+    if (lr > 0.f && (!adam_m || !adam_v || step < 1)) return fail(SCOCG_E_ARG, "Adam needs m, v and step >= 1");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nparts = (int64_t)scocg::GRAD_BLOCKS * 4;
+    float* partial = work;
+    float* loss_part = work + nparts * scocg::NPARAM;
+    (void)hipGetLastError();
+    HIP_TRY(scocg::launch_mlp_grad(w, x, t, idx, m, partial, loss_part, scocg::GRAD_BLOCKS, st));
+    HIP_TRY(scocg::launch_mlp_adam(w, adam_m, adam_v, partial, loss_part, nparts, m, lr, step, grad, loss, st));
     return SCOCG_OK;
 }

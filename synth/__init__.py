@@ -7,5 +7,5 @@ inner product or runs an iteration.
 """
 from .tb import (  # noqa: F401
     Bsr, Problem, CONFIGS, make_config, make_problem, lattice_sc, lattice_fcc,
-    cluster_offsets_fcc, cluster_offsets_sc, bsr_to_dense, bsr_to_scipy,
+    cluster_offsets_fcc, cluster_offsets_sc, bsr_to_dense, bsr_to_scipy, rngs_for, mlp_init_weights,
 )

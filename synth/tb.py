@@ -428,3 +428,16 @@ def bsr_to_scipy(A: Bsr):
 
 def bsr_to_dense(A: Bsr) -> np.ndarray:
     return bsr_to_scipy(A).toarray()
+
+
+# ----------------------------------------------------------------------------
+# random draws for the RHS-cost network (initial weights, batch order)
+# ----------------------------------------------------------------------------
+
+def mlp_init_weights(rng, nin=16, nh=64):
+    """Kaiming-uniform initial weights U(-sqrt(6/fan_in), +sqrt(6/fan_in)),
+    zero biases, in the layout W1[nh][nin], b1, W2[nh][nh], b2, W3[nh], b3."""
+    w1 = rng.uniform(-np.sqrt(6.0 / nin), np.sqrt(6.0 / nin), size=nh * nin)
+    w2 = rng.uniform(-np.sqrt(6.0 / nh), np.sqrt(6.0 / nh), size=nh * nh)
+    w3 = rng.uniform(-np.sqrt(6.0 / nh), np.sqrt(6.0 / nh), size=nh)
+    return np.concatenate([w1, np.zeros(nh), w2, np.zeros(nh), w3, np.zeros(1)])
