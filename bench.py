@@ -120,6 +120,33 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_bytes": n * 8, "seconds": dt, "GB/s": 2 * n * 8 / dt / 1e9}), flush=True)
 
 
+def plain_baseline(B, P, prob, args, kw):
+    """FP64 plain: the same library in FP64, full-x form, one RHS at a time
+    (one resident workgroup), index order; timed over the first args.plain RHS."""
+    import torch
+    sub = prob.subset(range(min(args.plain, prob.nrhs)))
+    kw = dict(kw, out_ptr=sub.out_ptr, out_rows=sub.out_rows)
+    if sub.cluster_ptr is not None:
+        kw.update(cluster_ptr=sub.cluster_ptr, cluster_atoms=sub.cluster_atoms)
+    plan = B.Plan(P, sub.shifts, sub.rhs, tol=args.tol, precision=0, audit=1, projected=0, slots=1, **kw)
+    bufs = plan.alloc_outputs()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    plan.run(bufs, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    status = bufs["status"].cpu().numpy()
+    resid = bufs["resid"].cpu().numpy()
+    good = int(np.sum((status == 0) & (resid <= 1e-6)))
+    out = {"metric": "FP64 plain baseline (not the product configuration)", "value": good / sec, "unit": "solves/s",
+           "workload": args.workload, "rhs_timed": sub.nrhs, "seconds": sec, "converged_pairs": good,
+           "form": "full x, one RHS at a time (1 workgroup), FP64", "threads": plan.info["threads"]}
+    print(json.dumps(out), flush=True)
+
+
 def _kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -160,6 +187,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--projected", type=int, default=1, help="FP64 SELECTED_G: rows-only solve (default 1)")
     ap.add_argument("--copy-calib", type=int, default=0, help="only run a device copy of this many bytes")
+    ap.add_argument("--no-autotune", action="store_true", help="use --threads/--slots as given")
+    ap.add_argument("--plain", type=int, default=0,
+                    help="measure FP64 plain instead: full x, one RHS at a time, on this many RHS")
     ap.add_argument("--maxiter", type=int, default=0,
                     help="diagnostics only: cap outer iterations (changes the workload; not a metric run)")
     args = ap.parse_args()
@@ -185,6 +215,16 @@ def main():
     kw = dict(out_ptr=prob.out_ptr, out_rows=prob.out_rows)
     if prob.cluster_ptr is not None:
         kw.update(cluster_ptr=prob.cluster_ptr, cluster_atoms=prob.cluster_atoms)
+    if args.plain:
+        return plain_baseline(B, P, prob, args, kw)
+    tuned = None
+    if not args.no_autotune and not args.threads and not args.slots:
+        tuned = B.autotune(P, prob.shifts, prob.rhs, probe_iters=50,
+                           cache_path=os.path.join(ROOT, "paper_1402_7285_amd", "autotune_cache.json"),
+                           key_extra=f"{args.workload}|{args.nrhs}", tol=args.tol, precision=PREC[args.precision],
+                           projected=args.projected, **kw)
+        args.threads, args.slots = tuned["threads"], tuned["slots"]
+        print(f"[bench] autotuned: {tuned}", file=sys.stderr, flush=True)
     plan = B.Plan(P, prob.shifts, prob.rhs, tol=args.tol, precision=PREC[args.precision], audit=1,
                   threads=args.threads, slots=args.slots, projected=args.projected, maxiter=args.maxiter, **kw)
     projected = bool(plan.info["global"] & 2)
@@ -226,7 +266,8 @@ def main():
         "config": {"workload": f"{args.workload}: {wl['desc']}", "nrhs": prob.nrhs, "shifts": prob.nshift,
                    "M": prob.M, "tol": args.tol, "precision": args.precision, "batched": "persistent",
                    "slots": plan.info["slots"], "threads": plan.info["threads"],
-                   "form": "projected rows (three-term seed)" if projected else "full x"},
+                   "form": "projected rows (three-term seed)" if projected else "full x",
+                   "autotuned": tuned is not None},
         "converged_pairs": good, "pairs": int(status.size),
         "outer_iterations": {"mean": float(stats[:, 0].mean()), "max": int(stats[:, 0].max())},
         "inner_per_outer": float(stats[:, 2].sum() / max(1, stats[:, 0].sum())),
