@@ -67,6 +67,34 @@ __device__ __forceinline__ float  bval(const bf16_t* p, int64_t i) {
 }
 
 // ---------------------------------------------------------------------------
+// quad broadcast: every lane of a group of four gets lane C's value (DPP
+// quad_perm, no LDS traffic).  Used where the four rows of a 4x4 block row
+// sit in the four lanes of a quad and each needs all four vector entries.
+// ---------------------------------------------------------------------------
+template <int C>
+__device__ __forceinline__ int quad_bcast_i32(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, C * 0x55, 0xF, 0xF, false);
+}
+template <int C>
+__device__ __forceinline__ double quad_bcast(double v) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)quad_bcast_i32<C>((int)(unsigned)(b & 0xffffffffLL));
+    const unsigned hi = (unsigned)quad_bcast_i32<C>((int)(unsigned)((unsigned long long)b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int C>
+__device__ __forceinline__ float quad_bcast(float v) {
+    return __int_as_float(quad_bcast_i32<C>(__float_as_int(v)));
+}
+template <int C, class V>
+__device__ __forceinline__ V quad_bcast2(const V& v) {
+    V o;
+    o.x = quad_bcast<C>(v.x);
+    o.y = quad_bcast<C>(v.y);
+    return o;
+}
+
+// ---------------------------------------------------------------------------
 // workgroup reductions (deterministic)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {

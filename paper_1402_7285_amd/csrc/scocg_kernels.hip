@@ -87,43 +87,91 @@ __device__ inline Lds lds_carve(unsigned char* base, int K, int NT) {
     return L;
 }
 
+// Row sums over the block entries of one row (row r of block row a):
+// h += H_row . p and s += S_row . p, entries in CSR order.  The entries are
+// visited in chunks of CH whose column and block indices are loaded together
+// and whose block and vector loads are then all in flight at once, so a row
+// costs a couple of memory latencies instead of one dependent chain per
+// entry.  A chunk's slots past the end of the row re-read the row's last
+// entry and contribute zero (so the sums equal the plain entry-by-entry ones).
+// For 4x4 blocks the four rows of a block row are the four lanes of a quad
+// (rows are dealt to threads in order and NT is a multiple of 64): each lane
+// loads one entry of the vector block and the quad shares them by DPP, which
+// quarters the vector loads and their registers.
+template <int BD, int NT, int NMAT>
+struct RowChunk {
+    static constexpr int base = BD == 1 ? 8 : (BD <= 4 ? 4 : 2);
+    static constexpr int v = base / (NT >= 1024 ? 2 : 1) / NMAT;
+    static constexpr int value = v < 1 ? 1 : v;
+};
+
+template <int BD, int NT, class TV, class TB, bool WITH_H, bool WITH_S>
+__device__ __forceinline__ void row_sums(const TB* __restrict__ H, const TB* __restrict__ S, const Sys& sy, int a,
+                                         int r, const v2<TV>* __restrict__ p, TV& hr, TV& hi, TV& sr, TV& si) {
+    constexpr int CH = RowChunk<BD, NT, (WITH_H ? 1 : 0) + (WITH_S ? 1 : 0)>::value;
+    constexpr bool QUAD = BD == 4 && NT % 64 == 0;
+    const int64_t e0 = sy.rowptr[a], e1 = sy.rowptr[a + 1];
+    for (int64_t eb = e0; eb < e1; eb += CH) {
+        int32_t b[CH], g[CH];
+        bool ok[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            ok[u] = eb + u < e1;
+            const int64_t e = ok[u] ? eb + u : e1 - 1;
+            b[u] = sy.ecol[e];
+            g[u] = sy.egid[e];
+        }
+        // all loads of the chunk first, then the arithmetic
+        v2<TV> own[QUAD ? CH : 1];
+        TV hv[WITH_H ? CH : 1][BD], sv[WITH_S ? CH : 1][BD];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int64_t off = ((int64_t)g[u] * BD + r) * BD;
+            if constexpr (QUAD) own[u] = p[(int64_t)b[u] * BD + r];
+#pragma unroll
+            for (int c = 0; c < BD; ++c) {
+                if constexpr (WITH_H) hv[u][c] = (TV)bval(H + off, c);
+                if constexpr (WITH_S) sv[u][c] = (TV)bval(S + off, c);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const v2<TV>* pb = p + (int64_t)b[u] * BD;
+#pragma unroll
+            for (int c = 0; c < BD; ++c) {
+                v2<TV> pv;
+                if constexpr (QUAD) {
+                    if (c == 0) pv = quad_bcast2<0>(own[u]);
+                    else if (c == 1) pv = quad_bcast2<1>(own[u]);
+                    else if (c == 2) pv = quad_bcast2<2>(own[u]);
+                    else pv = quad_bcast2<3>(own[u]);
+                } else {
+                    pv = pb[c];
+                }
+                if constexpr (WITH_H) {
+                    const TV h = ok[u] ? hv[u][c] : (TV)0;
+                    hr += h * pv.x;
+                    hi += h * pv.y;
+                }
+                if constexpr (WITH_S) {
+                    const TV sc = ok[u] ? sv[u][c] : (TV)0;
+                    sr += sc * pv.x;
+                    si += sc * pv.y;
+                }
+            }
+        }
+    }
+}
+
 // q = (z S - H) p over this thread's rows; returns the partial p^T q.
 template <int BD, int NT, class TV, class TB, bool SID>
 __device__ __forceinline__ zc op_apply(const TB* __restrict__ H, const TB* __restrict__ S, const Sys& sy, zc z,
                                        const v2<TV>* __restrict__ p, v2<TV>* __restrict__ q) {
     zc mu = zmk(0.0, 0.0);
-#pragma unroll 4
     for (int i = threadIdx.x; i < sy.M; i += NT) {
         const int a = i / BD, r = i - a * BD;
-        const int64_t e0 = sy.rowptr[a], e1 = sy.rowptr[a + 1];
         TV hr = 0, hi = 0, sr = 0, si = 0;
-        for (int64_t e = e0; e < e1; ++e) {
-            const int64_t b = sy.ecol[e];
-            const int64_t g = sy.egid[e];
-            const TB* hb = H + (g * BD + r) * BD;
-            const v2<TV>* pb = p + b * BD;
-            if constexpr (SID) {
-#pragma unroll
-                for (int c = 0; c < BD; ++c) {
-                    const v2<TV> pv = pb[c];
-                    const TV h = (TV)bval(hb, c);
-                    hr += h * pv.x;
-                    hi += h * pv.y;
-                }
-            } else {
-                const TB* sb = S + (g * BD + r) * BD;
-#pragma unroll
-                for (int c = 0; c < BD; ++c) {
-                    const v2<TV> pv = pb[c];
-                    const TV h = (TV)bval(hb, c);
-                    const TV s = (TV)bval(sb, c);
-                    hr += h * pv.x;
-                    hi += h * pv.y;
-                    sr += s * pv.x;
-                    si += s * pv.y;
-                }
-            }
-        }
+        row_sums<BD, NT, TV, TB, true, !SID>(H, S, sy, a, r, p, hr, hi, sr, si);
         const zc pi_ = ld<TV>(p, i);
         const zc sp = SID ? pi_ : zmk((double)sr, (double)si);
         const zc qv = rnd<TV>(zsub(zmul(z, sp), zmk((double)hr, (double)hi)));
@@ -138,24 +186,10 @@ template <int BD, int NT, class TV, class TB>
 __device__ __forceinline__ double spmv_S(const TB* __restrict__ S, const Sys& sy, const v2<TV>* __restrict__ d,
                                          v2<TV>* __restrict__ w) {
     double part = 0.0;
-#pragma unroll 4
     for (int i = threadIdx.x; i < sy.M; i += NT) {
         const int a = i / BD, r = i - a * BD;
-        const int64_t e0 = sy.rowptr[a], e1 = sy.rowptr[a + 1];
-        TV sr = 0, si = 0;
-        for (int64_t e = e0; e < e1; ++e) {
-            const int64_t b = sy.ecol[e];
-            const int64_t g = sy.egid[e];
-            const TB* sb = S + (g * BD + r) * BD;
-            const v2<TV>* db = d + b * BD;
-#pragma unroll
-            for (int c = 0; c < BD; ++c) {
-                const v2<TV> dv = db[c];
-                const TV s = (TV)bval(sb, c);
-                sr += s * dv.x;
-                si += s * dv.y;
-            }
-        }
+        TV hr = 0, hi = 0, sr = 0, si = 0;
+        row_sums<BD, NT, TV, TB, false, true>(S, S, sy, a, r, d, hr, hi, sr, si);
         const zc ws = rnd<TV>(zmk((double)sr, (double)si));
         st<TV>(w, i, ws);
         const zc dv = ld<TV>(d, i);
