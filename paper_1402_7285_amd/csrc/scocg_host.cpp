@@ -277,16 +277,32 @@ extern "C" scocg_status scocg_problem_create(const scocg_matrix* H, const scocg_
         p->has_S = S != nullptr;
         const int bd = p->bd, bb = bd * bd;
         p->rowptr.assign(p->nb + 1, 0);
-        // merged pattern: per row, the sorted union of H's and S's columns
+        // merged pattern: per row, the sorted union of H's and S's columns and
+        // the diagonal block (zero where neither has it), so that every block
+        // row, also of every cluster, has at least one entry: the kernels'
+        // chunked row sums re-read a row's last entry to fill a chunk.
         for (int64_t a = 0; a < p->nb; ++a) {
             int64_t i = H->rowptr[a], ie = H->rowptr[a + 1];
             int64_t j = S ? S->rowptr[a] : 0, je = S ? S->rowptr[a + 1] : 0;
-            while (i < ie || j < je) {
-                int32_t c;
-                const bool th = i < ie && (j >= je || H->col[i] <= S->col[j]);
-                const bool ts = j < je && (i >= ie || S->col[j] <= H->col[i]);
-                c = th ? H->col[i] : S->col[j];
-                p->col.push_back(c);
+            bool diag_done = false;
+            while (i < ie || j < je || !diag_done) {
+                const int32_t ch = i < ie ? H->col[i] : INT32_MAX;
+                const int32_t cs = j < je ? S->col[j] : INT32_MAX;
+                const int32_t cm = std::min(ch, cs);
+                if (!diag_done && a <= cm) {
+                    if (a < cm) {   // no stored diagonal block: a zero one
+                        p->col.push_back((int32_t)a);
+                        for (int t = 0; t < bb; ++t) p->hH.push_back(0.0);
+                        if (S)
+                            for (int t = 0; t < bb; ++t) p->hS.push_back(0.0);
+                        diag_done = true;
+                        continue;
+                    }
+                    diag_done = true;
+                }
+                const bool th = ch == cm && i < ie;
+                const bool ts = cs == cm && j < je;
+                p->col.push_back(cm);
                 for (int t = 0; t < bb; ++t) p->hH.push_back(th ? H->val[i * bb + t] : 0.0);
                 if (S)
                     for (int t = 0; t < bb; ++t) p->hS.push_back(ts ? S->val[j * bb + t] : 0.0);
