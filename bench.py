@@ -30,6 +30,12 @@ WORKLOADS = {
     "cfg0": dict(cfg=0, desc="shifted COCG S=I, simple-cubic 4^3, 4x4 blocks (M=256), 32 shifts + 0.05i, 8 RHS"),
     "cfg2": dict(cfg=2, desc="order-N clusters r~U[2,4]a on fcc 32^3, 9x9 blocks (M=1179648), "
                              "256 shifts + 0.01i, 4096 RHS"),
+    "cfg2r": dict(cfg=2, radius=(1.0, 2.0),
+                  desc="configuration 2 with cluster radii r~U[1,2]a (19-135 atoms, M_j 171-1215): fcc 32^3, "
+                       "9x9 blocks (M=1179648), 256 shifts + 0.01i, 4096 RHS"),
+    "cfg4r": dict(cfg=4, radius=(1.0, 2.0),
+                  desc="configuration 4 with cluster radii r~U[1,2]a: 16384 fresh RHS on configuration 2's "
+                       "matrices, 256 shifts + 0.01i"),
 }
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 
@@ -121,14 +127,19 @@ def copy_calibration(nbytes):
 
 
 def plain_baseline(B, P, prob, args, kw):
-    """FP64 plain: the same library in FP64, full-x form, one RHS at a time
-    (one resident workgroup), index order; timed over the first args.plain RHS."""
+    """FP64 plain: the same library in FP64, textbook full-x form (every
+    shift's x and p over the whole local system, two-term seed), no
+    projection and no lower precision; the first args.plain RHS run
+    concurrently, one workgroup each (the kernel's per-RHS time does not
+    shrink with fewer RHS, so this is the plain form's rate on that many
+    compute units)."""
     import torch
     sub = prob.subset(range(min(args.plain, prob.nrhs)))
     kw = dict(kw, out_ptr=sub.out_ptr, out_rows=sub.out_rows)
     if sub.cluster_ptr is not None:
         kw.update(cluster_ptr=sub.cluster_ptr, cluster_atoms=sub.cluster_atoms)
-    plan = B.Plan(P, sub.shifts, sub.rhs, tol=args.tol, precision=0, audit=1, projected=0, slots=1, **kw)
+    plan = B.Plan(P, sub.shifts, sub.rhs, tol=args.tol, precision=0, audit=1, projected=0, slots=sub.nrhs,
+                  threads=args.threads, **kw)
     bufs = plan.alloc_outputs()
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -143,7 +154,91 @@ def plain_baseline(B, P, prob, args, kw):
     good = int(np.sum((status == 0) & (resid <= 1e-6)))
     out = {"metric": "FP64 plain baseline (not the product configuration)", "value": good / sec, "unit": "solves/s",
            "workload": args.workload, "rhs_timed": sub.nrhs, "seconds": sec, "converged_pairs": good,
-           "form": "full x, one RHS at a time (1 workgroup), FP64", "threads": plan.info["threads"]}
+           "form": "full x, FP64, one workgroup per RHS, all RHS concurrent", "threads": plan.info["threads"],
+           "slots": plan.info["slots"]}
+    print(json.dumps(out), flush=True)
+
+
+def binning_ab(B, args):
+    """Learned binning, measured: solve the training workload and log each
+    RHS's outer-iteration count, train the cost network on the GPU on those
+    counts, then time the test workload (args.workload) with the work queue
+    in index order, by local-pattern size, by the learned cost and by the
+    true cost (known from the index-order solve).  Results must be identical
+    in every order; only the time changes."""
+    import torch
+    from paper_1402_7285_amd import binning
+    from synth import make_config, mlp_init_weights, rngs_for
+
+    def setup(name):
+        wl = WORKLOADS[name]
+        prob = make_config(wl["cfg"], radius=wl.get("radius"))
+        P = B.Problem(prob.H, prob.S)
+        kw = dict(out_ptr=prob.out_ptr, out_rows=prob.out_rows)
+        if prob.cluster_ptr is not None:
+            kw.update(cluster_ptr=prob.cluster_ptr, cluster_atoms=prob.cluster_atoms)
+        return prob, P, kw
+
+    def timed(P, prob, kw, order=None):
+        plan = B.Plan(P, prob.shifts, prob.rhs, tol=args.tol, threads=args.threads, slots=args.slots,
+                      order=order, **kw)
+        bufs = plan.alloc_outputs()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.run(bufs)
+        e1.record()
+        torch.cuda.synchronize()
+        return plan, bufs, e0.elapsed_time(e1) / 1e3
+
+    ptr, Ptr, kwtr = setup(args.binning)
+    print(f"[binning] training workload {args.binning}: {ptr.nrhs} RHS", file=sys.stderr, flush=True)
+    plan, bufs, sec = timed(Ptr, ptr, kwtr)
+    st = plan.stats()
+    feats = plan.features().cpu().numpy()
+    print(f"[binning] training solve {sec:.1f} s", file=sys.stderr, flush=True)
+    rg = rngs_for((1402, 7285, 4))
+    t0 = time.perf_counter()
+    model = binning.train(feats, np.log(st[:, 0].astype(np.float64)), mlp_init_weights(rg["mlp_init"]),
+                          rg["mlp_shuffle"], epochs=args.binning_epochs, batch=256, lr=3e-3)
+    t_train = time.perf_counter() - t0
+    best_val = float(min(h[2] for h in model.history))
+    print(f"[binning] trained in {t_train:.1f} s, best validation MSE {best_val:.3f}", file=sys.stderr, flush=True)
+    del plan, bufs, Ptr
+    torch.cuda.empty_cache()
+
+    pte, Pte, kwte = setup(args.workload)
+    plan0, bufs0, sec_index = timed(Pte, pte, kwte)
+    ref = bufs0["out"].cpu()
+    st0 = plan0.stats()
+    ft = plan0.features().cpu().numpy()
+    print(f"[binning] test workload {args.workload}: {pte.nrhs} RHS, index order {sec_index:.1f} s",
+          file=sys.stderr, flush=True)
+    del bufs0
+    pred = binning.predict(model, ft)
+    truth = st0[:, 0].astype(np.float64)
+    ent = binning.entries_per_rhs(ft)
+    corr = float(np.corrcoef(pred, np.log(truth))[0, 1])
+    orders = {"by_size": binning.order_longest_first(ent),
+              "learned": binning.order_longest_first(np.exp(pred) * ent),
+              "true_cost": binning.order_longest_first(truth * ent)}
+    times = {"index": sec_index}
+    for name, order in orders.items():
+        _, b, sec = timed(Pte, pte, kwte, order=order)
+        same = bool(torch.equal(b["out"].cpu(), ref))
+        times[name] = sec
+        print(f"[binning] {name} order {sec:.1f} s, results identical: {same}", file=sys.stderr, flush=True)
+        if not same:
+            raise SystemExit("queue order changed the results")
+        del b
+    pairs = pte.nrhs * pte.nshift
+    out = {"metric": "learned binning: solve time by work-queue order", "unit": "s",
+           "train_workload": args.binning, "test_workload": args.workload, "nrhs_test": pte.nrhs,
+           "seconds": times, "solves_per_s": {k: pairs / v for k, v in times.items()},
+           "gain_learned_vs_index": times["index"] / times["learned"],
+           "gain_learned_vs_by_size": times["by_size"] / times["learned"],
+           "pred_corr_log_iters": corr, "best_val_mse": best_val, "train_seconds": t_train,
+           "slots": plan0.info["slots"], "threads": plan0.info["threads"]}
     print(json.dumps(out), flush=True)
 
 
@@ -190,6 +285,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="use --threads/--slots as given")
     ap.add_argument("--plain", type=int, default=0,
                     help="measure FP64 plain instead: full x, one RHS at a time, on this many RHS")
+    ap.add_argument("--binning", default="",
+                    help="measure learned binning: train on this workload's logs, time --workload's queue orders")
+    ap.add_argument("--binning-epochs", type=int, default=150)
     ap.add_argument("--maxiter", type=int, default=0,
                     help="diagnostics only: cap outer iterations (changes the workload; not a metric run)")
     args = ap.parse_args()
@@ -207,8 +305,10 @@ def main():
     from synth import make_config
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.binning:
+        return binning_ab(B, args)
     wl = WORKLOADS[args.workload]
-    prob = make_config(wl["cfg"], nrhs=args.nrhs or None)
+    prob = make_config(wl["cfg"], nrhs=args.nrhs or None, radius=wl.get("radius"))
     print(f"[bench] {args.workload}: M={prob.M} K={prob.nshift} nrhs={prob.nrhs} precision={args.precision}",
           file=sys.stderr, flush=True)
     P = B.Problem(prob.H, prob.S)

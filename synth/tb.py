@@ -387,17 +387,26 @@ def _cfg_kwargs(cfg, L=None):
     return c
 
 
-def make_config(cfg: int, nrhs: Optional[int] = None, L: Optional[int] = None) -> Problem:
+def make_config(cfg: int, nrhs: Optional[int] = None, L: Optional[int] = None,
+                radius: Optional[tuple] = None) -> Problem:
     """Build one of the named workloads.
 
     ``nrhs`` keeps only the first ``nrhs`` RHS in generation order (the
     matrices and the remaining draws are unchanged).  ``L`` shrinks the
     lattice for quick tests (the draws then differ from the full workload).
+    ``radius`` replaces the cluster-radius range of configurations 2-4 (in
+    lattice constants; the matrices, RHS indices and random streams are
+    unchanged, only the uniform radii are rescaled to the new range).
     Configurations 3 and 4 use the matrices of configuration 2; 3 also uses
     its RHS, 4 draws fresh RHS disjoint from configuration 2's.
     """
     name = CONFIGS[cfg]["name"]
     c = _cfg_kwargs(cfg, L)
+    if radius is not None:
+        if "radius" not in c:
+            raise ValueError("configuration has no clusters")
+        c["radius"] = tuple(radius)
+        name = name + f"_r{radius[0]:g}-{radius[1]:g}"
     full_nrhs = c["nrhs"]
     exclude = None
     if cfg == 3:
