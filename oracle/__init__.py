@@ -11,4 +11,4 @@ from .scocg import (  # noqa: F401
     inner_cg, scocg, scocg_projected, local_system, solve_rhs, solve_problem,
 )
 from .dense import dense_solve, green_eig, true_residual  # noqa: F401
-from . import mlp, features  # noqa: F401
+from . import mlp, features, integrate  # noqa: F401
