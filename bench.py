@@ -378,6 +378,23 @@ def main():
                      "kernel": "k_scocg (persistent solver)", "kernel_ms": kernel_s * 1e3,
                      "algorithmic_bytes": alg},
     }
+    w = np.zeros(prob.nshift)
+    if prob.nshift > 1:
+        dE = np.diff(prob.shifts.real)
+        w[:-1] += 0.5 * dE
+        w[1:] += 0.5 * dE
+    plan.integrate(bufs, w, 0.0, 0.1)                     # warm
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    rho, ldos = plan.integrate(bufs, w, 0.0, 0.1, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_int = e0.elapsed_time(e1)
+    int_bytes = plan.out_count * prob.nshift * 16 + plan.out_count * 8 + prob.nrhs * prob.nshift * 8
+    out["energy_integration"] = {"ms": ms_int, "bytes": int_bytes, "GB/s": int_bytes / (ms_int * 1e-3) / 1e9,
+                                 "what": "density-matrix rows and local DOS from the computed G (trapezoid, "
+                                         "mu = 0, kT = 0.1)"}
     if not args.no_cpu_baseline:
         workers = max(1, min(16, os.cpu_count() or 1))
         print(f"[bench] cpu baseline: oracle on {workers} processes ...", file=sys.stderr, flush=True)

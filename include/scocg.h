@@ -91,7 +91,7 @@ const char* scocg_version(void);
  * The arrays are copied; the caller keeps ownership of its buffers.  The
  * matrix must be exactly symmetric: for every block (a,b) the block (b,a)
  * must be present and equal to its transpose (SCOCG_E_NOT_SYMMETRIC).
- * bdim must be 1..16 (the solver runs bdim 4 and 9; others give
+ * bdim must be 1..16 (the solver runs bdim 1, 4 and 9; others give
  * SCOCG_E_UNSUPPORTED at plan creation).
  */
 scocg_status scocg_matrix_from_bsr(int64_t nbrows, int32_t bdim, const int64_t* rowptr,
@@ -104,6 +104,26 @@ scocg_status scocg_matrix_from_bsr(int64_t nbrows, int32_t bdim, const int64_t* 
  */
 scocg_status scocg_matrix_from_csr(int64_t n, const int64_t* rowptr, const int32_t* colidx,
                                    const double* vals, int32_t bdim, scocg_matrix** out);
+
+/*
+ * Same from a Matrix Market file (`%%MatrixMarket matrix coordinate real
+ * symmetric|general`, 1-based entries; the form in which published
+ * tight-binding matrix sets are distributed, cf. the matrix library of
+ * Sec. 6).  A symmetric file's stored triangle is mirrored; duplicate
+ * entries are summed; then as scocg_matrix_from_csr with the given bdim
+ * (1 reads matrices with mixed orbital counts per atom).  Errors: E_ARG
+ * (NULL, file cannot be opened), E_SHAPE (not a real coordinate matrix,
+ * not square, bad or missing lines, index out of range), and those of the
+ * CSR path (E_NOT_SYMMETRIC for a general file that is not symmetric).
+ */
+scocg_status scocg_matrix_from_mtx(const char* path, int32_t bdim, scocg_matrix** out);
+
+/* Shape of a matrix: block rows, block dimension, stored blocks. */
+scocg_status scocg_matrix_shape(const scocg_matrix* m, int64_t* nbrows, int32_t* bdim, int64_t* nblocks);
+
+/* Copy the stored BSR arrays out (caller-allocated host arrays of the
+ * sizes scocg_matrix_shape gives: nbrows+1, nblocks, nblocks*bdim*bdim). */
+scocg_status scocg_matrix_export_bsr(const scocg_matrix* m, int64_t* rowptr, int32_t* colidx, double* vals);
 
 void scocg_matrix_free(scocg_matrix* m);
 
@@ -288,6 +308,22 @@ scocg_status scocg_mlp_forward(const float* w, const float* x, int64_t n, float*
 scocg_status scocg_mlp_train_step(float* w, float* adam_m, float* adam_v, const float* x, const float* t,
                                   const int32_t* idx, int64_t m, float lr, int32_t step, float* loss,
                                   float* grad, float* work, void* stream);
+
+/* Energy integration of G (the density of states and the density matrix,
+ * Sec. 2-3: the Green's function as the analysis object).  G is the output
+ * buffer a previous scocg_plan_run of this plan wrote ([rhs][shift][row],
+ * SELECTED_G or FULL_X).  For every output row o of RHS j:
+ *   rho[o] = -(1/pi) sum_k weights[k] f(Re z_k) Im G_{row(o), j}(z_k),
+ * with f(E) = 1/(1 + exp((E - mu)/kT)) (kT = 0: a step, 1/2 at E = mu), and,
+ * if ldos is not NULL, ldos[j*nshift + k] = -(1/pi) Im G_jj(z_k) (NaN when
+ * orbital j is not among RHS j's output rows).  weights: the caller's
+ * quadrature weights on the real parts of the shifts (e.g. trapezoid for an
+ * equally spaced mesh).  G, weights, rho (out_count doubles) and ldos
+ * (nrhs*nshift doubles) are device pointers owned by the caller; the call is
+ * asynchronous on `stream`.  Errors: E_ARG (NULL pointer, non-finite mu,
+ * negative or non-finite kT), E_DEVICE. */
+scocg_status scocg_plan_integrate(scocg_plan* plan, void* stream, const scocg_z* G, const double* weights,
+                                  double mu, double kT, double* rho, double* ldos);
 
 /*
  * Per-RHS counters of the last run, copied to host int64[nrhs * SCOCG_NSTAT]

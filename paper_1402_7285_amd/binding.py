@@ -31,7 +31,8 @@ EXPORTS = (
     "scocg_plan_create", "scocg_plan_free", "scocg_plan_out_count", "scocg_plan_out_offsets", "scocg_plan_info",
     "scocg_plan_run", "scocg_plan_stats", "scocg_solve", "scocg_plan_capture", "scocg_plan_replay",
     "scocg_autotune", "scocg_features", "scocg_mlp_nparams", "scocg_mlp_work_floats", "scocg_mlp_forward",
-    "scocg_mlp_train_step",
+    "scocg_mlp_train_step", "scocg_plan_integrate", "scocg_matrix_from_mtx", "scocg_matrix_shape",
+    "scocg_matrix_export_bsr",
 )
 
 
@@ -69,6 +70,9 @@ def _declare(lib):
         "scocg_matrix_from_bsr": (st, [i64, i32, _VP, _VP, _VP, C.POINTER(_VP)]),
         "scocg_matrix_from_csr": (st, [i64, _VP, _VP, _VP, i32, C.POINTER(_VP)]),
         "scocg_matrix_free": (None, [_VP]),
+        "scocg_matrix_from_mtx": (st, [C.c_char_p, i32, C.POINTER(_VP)]),
+        "scocg_matrix_shape": (st, [_VP, C.POINTER(i64), C.POINTER(i32), C.POINTER(i64)]),
+        "scocg_matrix_export_bsr": (st, [_VP, _VP, _VP, _VP]),
         "scocg_problem_create": (st, [_VP, _VP, C.POINTER(_VP)]),
         "scocg_problem_free": (None, [_VP]),
         "scocg_options_default": (None, [C.POINTER(scocg_options)]),
@@ -83,6 +87,7 @@ def _declare(lib):
         "scocg_plan_capture": (st, [_VP, _VP, _VP, _VP, _VP, _VP]),
         "scocg_plan_replay": (st, [_VP, _VP]),
         "scocg_features": (st, [_VP, _VP, _VP]),
+        "scocg_plan_integrate": (st, [_VP, _VP, _VP, _VP, C.c_double, C.c_double, _VP, _VP]),
         "scocg_mlp_nparams": (i64, []),
         "scocg_mlp_work_floats": (i64, []),
         "scocg_mlp_forward": (st, [_VP, _VP, i64, _VP, _VP]),
@@ -254,6 +259,11 @@ def _sp(stream):
     return None if stream is None else C.c_void_p(stream.cuda_stream)
 
 
+def scocg_plan_integrate(h, G, weights, mu, kT, rho, ldos=None, stream=None):
+    return _check(load().scocg_plan_integrate(h, _sp(stream), _tptr(G), _tptr(weights), float(mu), float(kT),
+                                              _tptr(rho), _tptr(ldos)))
+
+
 def scocg_features(h, feats, stream=None):
     return _check(load().scocg_features(h, _tptr(feats), _sp(stream)))
 
@@ -308,7 +318,39 @@ class Matrix:
     @classmethod
     def from_bsr(cls, A):
         """From any object with nbrows, bdim, rowptr, colidx, vals attributes."""
+        if isinstance(A, Matrix):
+            return A
         return cls(A.nbrows, A.bdim, A.rowptr, A.colidx, A.vals)
+
+    @classmethod
+    def from_mtx(cls, path, bdim=1):
+        """Read a Matrix Market file (real coordinate, symmetric or general)."""
+        m = cls.__new__(cls)
+        h = _VP()
+        _check(load().scocg_matrix_from_mtx(os.fsencode(path), int(bdim), C.byref(h)))
+        m.h = h
+        return m
+
+    def shape(self):
+        """(block rows, block dimension, stored blocks)."""
+        nb, bd, nblk = C.c_int64(), C.c_int32(), C.c_int64()
+        _check(load().scocg_matrix_shape(self.h, C.byref(nb), C.byref(bd), C.byref(nblk)))
+        return nb.value, bd.value, nblk.value
+
+    def export(self):
+        """The stored BSR arrays as an object with nbrows, bdim, rowptr, colidx, vals."""
+        nb, bd, nblk = self.shape()
+        rp = np.empty(nb + 1, dtype=np.int64)
+        ci = np.empty(max(1, nblk), dtype=np.int32)
+        vv = np.empty((max(1, nblk), bd, bd), dtype=np.float64)
+        _check(load().scocg_matrix_export_bsr(self.h, rp.ctypes.data, ci.ctypes.data, vv.ctypes.data))
+
+        class _B:
+            pass
+        out = _B()
+        out.nbrows, out.bdim, out.rowptr, out.colidx, out.vals = nb, bd, rp, ci[:nblk], vv[:nblk]
+        out.n = nb * bd
+        return out
 
     def __del__(self):
         if getattr(self, "h", None) and _LIB is not None:
@@ -365,6 +407,19 @@ class Plan:
 
     def stats(self) -> np.ndarray:
         return scocg_plan_stats(self.h, self.nrhs)
+
+    def integrate(self, bufs, weights, mu, kT, stream=None):
+        """Density-matrix rows and local DOS from the G of the last run in
+        ``bufs``: returns (rho [out_count] float64, ldos [nrhs, K] float64),
+        torch CUDA tensors.  ``weights``: K quadrature weights (array-like)."""
+        import torch
+        w = torch.as_tensor(np.asarray(weights, dtype=np.float64)).to("cuda")
+        rho = torch.empty(max(1, self.out_count), dtype=torch.float64, device="cuda")
+        ldos = torch.empty((max(1, self.nrhs), self.K), dtype=torch.float64, device="cuda")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        scocg_plan_integrate(self.h, bufs["out"], w, mu, kT, rho, ldos, stream)
+        return rho[: self.out_count], ldos[: self.nrhs]
 
     def features(self):
         """[nrhs, 16] FP32 features computed on the device (torch tensor)."""

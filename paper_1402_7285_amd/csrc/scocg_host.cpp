@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cctype>
 #include <cstring>
 #include <new>
 #include <string>
@@ -240,6 +241,91 @@ extern "C" scocg_status scocg_matrix_from_csr(int64_t n, const int64_t* rowptr, 
         }
     }
     return scocg_matrix_from_bsr(nb, bdim, brp.data(), bcol.data(), bval.data(), out);
+}
+
+// Matrix Market coordinate files (real, symmetric or general), the format
+// of published tight-binding matrix sets: entries (i, j, v) 1-based; a
+// symmetric file stores one triangle and the other is mirrored here.
+// Duplicate entries are summed.  The result goes through the CSR path, so
+// the same exact-symmetry check applies.
+extern "C" scocg_status scocg_matrix_from_mtx(const char* path, int32_t bdim, scocg_matrix** out) {
+    if (!out || !path) return fail(SCOCG_E_ARG, "NULL argument");
+    *out = nullptr;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(SCOCG_E_ARG, "cannot open %s", path);
+    struct Closer {
+        FILE* f;
+        ~Closer() { std::fclose(f); }
+    } closer{f};
+    char line[4096];
+    if (!std::fgets(line, sizeof line, f)) return fail(SCOCG_E_SHAPE, "empty file");
+    std::string hdr(line);
+    for (auto& ch : hdr) ch = (char)std::tolower((unsigned char)ch);
+    if (hdr.rfind("%%matrixmarket", 0) != 0) return fail(SCOCG_E_SHAPE, "not a Matrix Market file");
+    if (hdr.find(" matrix ") == std::string::npos || hdr.find(" coordinate ") == std::string::npos)
+        return fail(SCOCG_E_SHAPE, "only 'matrix coordinate' files are read");
+    if (hdr.find(" real ") == std::string::npos && hdr.find(" integer ") == std::string::npos)
+        return fail(SCOCG_E_SHAPE, "only real (or integer) values are read");
+    const bool sym = hdr.find(" symmetric") != std::string::npos;
+    if (!sym && hdr.find(" general") == std::string::npos)
+        return fail(SCOCG_E_SHAPE, "symmetry must be 'symmetric' or 'general'");
+    long long nr = -1, nc = -1, nnz = -1;
+    while (std::fgets(line, sizeof line, f)) {
+        if (line[0] == '%' || line[0] == '\n' || line[0] == '\r') continue;
+        if (std::sscanf(line, "%lld %lld %lld", &nr, &nc, &nnz) != 3) return fail(SCOCG_E_SHAPE, "bad size line");
+        break;
+    }
+    if (nr <= 0 || nr != nc || nnz < 0 || nr > INT32_MAX) return fail(SCOCG_E_SHAPE, "matrix must be square");
+    struct Ent {
+        int32_t i, j;
+        double v;
+    };
+    std::vector<Ent> e;
+    e.reserve((size_t)(sym ? 2 * nnz : nnz));
+    long long got = 0;
+    while (got < nnz && std::fgets(line, sizeof line, f)) {
+        if (line[0] == '%' || line[0] == '\n' || line[0] == '\r') continue;
+        long long i, j;
+        double v;
+        if (std::sscanf(line, "%lld %lld %lf", &i, &j, &v) != 3) return fail(SCOCG_E_SHAPE, "bad entry line");
+        if (i < 1 || j < 1 || i > nr || j > nr) return fail(SCOCG_E_SHAPE, "entry index out of range");
+        e.push_back({(int32_t)(i - 1), (int32_t)(j - 1), v});
+        if (sym && i != j) e.push_back({(int32_t)(j - 1), (int32_t)(i - 1), v});
+        ++got;
+    }
+    if (got != nnz) return fail(SCOCG_E_SHAPE, "file ends after %lld of %lld entries", got, nnz);
+    std::sort(e.begin(), e.end(), [](const Ent& a, const Ent& b) { return a.i != b.i ? a.i < b.i : a.j < b.j; });
+    std::vector<int64_t> rp(nr + 1, 0);
+    std::vector<int32_t> ci;
+    std::vector<double> vv;
+    for (size_t t = 0; t < e.size(); ++t) {
+        if (!ci.empty() && t > 0 && e[t].i == e[t - 1].i && e[t].j == e[t - 1].j) {
+            vv.back() += e[t].v;
+            continue;
+        }
+        ci.push_back(e[t].j);
+        vv.push_back(e[t].v);
+        rp[e[t].i + 1] = (int64_t)ci.size();
+    }
+    for (long long r = 0; r < nr; ++r) rp[r + 1] = std::max(rp[r + 1], rp[r]);
+    return scocg_matrix_from_csr((int64_t)nr, rp.data(), ci.data(), vv.data(), bdim, out);
+}
+
+extern "C" scocg_status scocg_matrix_shape(const scocg_matrix* m, int64_t* nbrows, int32_t* bdim, int64_t* nblocks) {
+    if (!m || !nbrows || !bdim || !nblocks) return fail(SCOCG_E_ARG, "NULL argument");
+    *nbrows = m->nb;
+    *bdim = m->bd;
+    *nblocks = (int64_t)m->col.size();
+    return SCOCG_OK;
+}
+
+extern "C" scocg_status scocg_matrix_export_bsr(const scocg_matrix* m, int64_t* rowptr, int32_t* colidx,
+                                                double* vals) {
+    if (!m || !rowptr || !colidx || !vals) return fail(SCOCG_E_ARG, "NULL argument");
+    std::copy(m->rowptr.begin(), m->rowptr.end(), rowptr);
+    std::copy(m->col.begin(), m->col.end(), colidx);
+    std::copy(m->val.begin(), m->val.end(), vals);
+    return SCOCG_OK;
 }
 
 extern "C" void scocg_matrix_free(scocg_matrix* m) { delete m; }
@@ -811,6 +897,19 @@ extern "C" scocg_status scocg_plan_run(scocg_plan* pl, void* stream, scocg_z* ou
     (void)hipGetLastError();   // drop any error another caller left on this thread
     HIP_TRY(scocg::launch_fill_i32(pl->dqueue, 0, 1, st));
     HIP_TRY(scocg::launch_solver(k, P->bd, pl->proj ? 3 : pl->prec, !P->has_S, pl->nt, pl->slots, st));
+    return SCOCG_OK;
+}
+
+extern "C" scocg_status scocg_plan_integrate(scocg_plan* pl, void* stream, const scocg_z* G, const double* weights,
+                                             double mu, double kT, double* rho, double* ldos) {
+    if (!pl || !G || !weights || !rho) return fail(SCOCG_E_ARG, "NULL argument");
+    if (!std::isfinite(mu) || !std::isfinite(kT) || kT < 0.0) return fail(SCOCG_E_ARG, "mu must be finite, kT >= 0");
+    if (pl->nrhs == 0) return SCOCG_OK;
+    HIP_TRY(hipSetDevice(pl->P->device));
+    hipStream_t st = (hipStream_t)stream;
+    (void)hipGetLastError();
+    HIP_TRY(scocg::launch_integrate((const double*)G, pl->dz, weights, pl->drhs, pl->doutoff, pl->doutl, pl->nrhs,
+                                    pl->K, mu, kT, rho, ldos, st));
     return SCOCG_OK;
 }
 
