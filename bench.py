@@ -41,6 +41,22 @@ WORKLOADS = {
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 
+def algorithmic_bytes_qmr(stats, nout, bd, has_S, w_share):
+    """Algorithmic bytes of one launch of the shifted QMR solver (real
+    Lanczos vectors, 8 bytes per element).  Per RHS and iteration:
+      shifts  80 K_a n + 8 n          (read d_{n-1}, d_{n-2}, x; write d_n, x on n = |I_j| rows; v on them)
+      Lanczos nb_H b^2 8 / w_share + 96 M_j   (H v; t = u - alpha w - beta w_prev; q^T t; the rescale)
+      inner   k_in (nb_S b^2 8 / w_share + 48 M_j)"""
+    outer, sum_upd, inner = stats[:, 0].astype(float), stats[:, 1].astype(float), stats[:, 2].astype(float)
+    M, nblk = stats[:, 4].astype(float), stats[:, 5].astype(float)
+    n = np.asarray(nout, dtype=float)
+    blk = nblk * bd * bd * 8
+    shifts = sum_upd * n * 80 + outer * n * 8
+    lanczos = outer * (blk / w_share + 96 * M)
+    a5 = inner * (blk / w_share + 48 * M) if has_S else 0.0
+    return float(np.sum(shifts + lanczos + a5))
+
+
 def algorithmic_bytes(stats, nout, K, bd, has_S, prec, projected, w_share, audit):
     """Algorithmic bytes of one launch, from the per-unit figures of the
     design notes (FP64; FP32 halves vectors, blocks shrink to 4 or 2 bytes).
@@ -68,7 +84,7 @@ def algorithmic_bytes(stats, nout, K, bd, has_S, prec, projected, w_share, audit
 def cpu_baseline(prob, gpu_stats, n_rhs_sample, iters_sample, workers, projected):
     """Time the oracle (as it stands) on host cores: `workers` processes, each
     running `iters_sample` outer iterations of one RHS of the same workload
-    with the same form of the method (projected rows or full x); the measured
+    with the same form of the method (projected rows, full x, or "qmr"); the measured
     time per iteration times the mean outer iteration count the solve needs
     (from the GPU run) gives the time per RHS, hence solves/s."""
     import multiprocessing as mp
@@ -84,7 +100,7 @@ def cpu_baseline(prob, gpu_stats, n_rhs_sample, iters_sample, workers, projected
     rate = prob.nshift * min(workers, len(idx)) / t_rhs
     return dict(value=rate, unit="solves/s", cores=int(min(workers, len(idx))), kind="oracle",
                 sample=f"{len(idx)} RHS x {iters_sample} outer iterations of the same workload "
-                       f"({'projected rows, three-term form' if projected else 'full x'}), one RHS per "
+                       f"({'shifted QMR, real Lanczos basis' if projected == 'qmr' else 'projected rows, three-term form' if projected else 'full x'}), one RHS per "
                        f"process ({workers} processes, 1 BLAS thread each); t/iteration {t_iter * 1e3:.1f} ms "
                        f"x mean outer iterations {mean_outer:.0f} (GPU run) = {t_rhs:.0f} s per RHS of "
                        f"{prob.nshift} shifts; wall {wall:.1f} s")
@@ -92,12 +108,13 @@ def cpu_baseline(prob, gpu_stats, n_rhs_sample, iters_sample, workers, projected
 
 def _cpu_worker(args):
     prob, j, iters, projected = args
+    qmr = projected == "qmr"
     try:
         from threadpoolctl import threadpool_limits
         threadpool_limits(1)
     except Exception:
         pass
-    from oracle import local_system, scocg, scocg_projected
+    from oracle import local_system, scocg, scocg_projected, sqmr
     from synth import bsr_to_scipy
     H = bsr_to_scipy(prob.H)
     S = bsr_to_scipy(prob.S) if prob.S is not None else None
@@ -105,7 +122,10 @@ def _cpu_worker(args):
     b = np.zeros(orb.size, dtype=np.complex128)
     b[loc] = 1.0
     t0 = time.perf_counter()
-    if projected:
+    if qmr:
+        rows = np.searchsorted(orb, prob.outs(j))
+        res = sqmr(Hc, Sc, prob.shifts, b.real, 1e-6, rows=rows, maxiter=iters)
+    elif projected:
         rows = np.searchsorted(orb, prob.outs(j))
         res = scocg_projected(Hc, Sc, prob.shifts, b, rows, 1e-6, maxiter=iters)
     else:
@@ -256,7 +276,7 @@ def measured_traffic(args, projected):
     """HBM bytes per launch from the committed rocprofv3 counter summary of
     this workload (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading),
     or None if there is none or the kernel sources changed since."""
-    key = f"{args.workload}_{args.precision}_{'proj' if projected else 'full'}"
+    key = f"{args.workload}_{args.precision}_{'qmr' if args.method == 'qmr' else 'proj' if projected else 'full'}"
     path = os.path.join(ROOT, "profiles", f"k_scocg_{key}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -282,6 +302,8 @@ def main():
     ap.add_argument("--cpu-rhs", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--projected", type=int, default=1, help="FP64 SELECTED_G: rows-only solve (default 1)")
+    ap.add_argument("--method", default="cocg", choices=["cocg", "qmr"],
+                    help="cocg: shifted COCG with seed switching; qmr: shifted QMR over the real Lanczos basis")
     ap.add_argument("--copy-calib", type=int, default=0, help="only run a device copy of this many bytes")
     ap.add_argument("--no-autotune", action="store_true", help="use --threads/--slots as given")
     ap.add_argument("--plain", type=int, default=0,
@@ -323,12 +345,14 @@ def main():
         tuned = B.autotune(P, prob.shifts, prob.rhs, probe_iters=50,
                            cache_path=os.path.join(ROOT, "paper_1402_7285_amd", "autotune_cache.json"),
                            key_extra=f"{args.workload}|{args.nrhs}", tol=args.tol, precision=PREC[args.precision],
-                           projected=args.projected, **kw)
+                           projected=args.projected, method=int(args.method == "qmr"), **kw)
         args.threads, args.slots = tuned["threads"], tuned["slots"]
         print(f"[bench] autotuned: {tuned}", file=sys.stderr, flush=True)
     plan = B.Plan(P, prob.shifts, prob.rhs, tol=args.tol, precision=PREC[args.precision], audit=1,
-                  threads=args.threads, slots=args.slots, projected=args.projected, maxiter=args.maxiter, **kw)
+                  threads=args.threads, slots=args.slots, projected=args.projected, maxiter=args.maxiter,
+                  method=int(args.method == "qmr"), **kw)
     projected = bool(plan.info["global"] & 2)
+    qmr = bool(plan.info["global"] & 4)
     bufs = plan.alloc_outputs()
     stream = torch.cuda.current_stream()
     for w in range(args.warmup):
@@ -355,8 +379,11 @@ def main():
     value = good / (ms_per_step / 1e3)
     nout = np.diff(prob.out_ptr)
     w_share = min(plan.info["slots"], prob.nrhs) if prob.cluster_ptr is None else 1
-    alg = algorithmic_bytes(stats, nout, prob.nshift, prob.bdim, prob.S is not None, PREC[args.precision],
-                            projected, w_share, True)
+    if qmr:
+        alg = algorithmic_bytes_qmr(stats, nout, prob.bdim, prob.S is not None, w_share)
+    else:
+        alg = algorithmic_bytes(stats, nout, prob.nshift, prob.bdim, prob.S is not None, PREC[args.precision],
+                                projected, w_share, True)
     achieved = alg / kernel_s / 1e9
     traffic = measured_traffic(args, projected)
     out = {
@@ -367,7 +394,8 @@ def main():
         "config": {"workload": f"{args.workload}: {wl['desc']}", "nrhs": prob.nrhs, "shifts": prob.nshift,
                    "M": prob.M, "tol": args.tol, "precision": args.precision, "batched": "persistent",
                    "slots": plan.info["slots"], "threads": plan.info["threads"],
-                   "form": "projected rows (three-term seed)" if projected else "full x",
+                   "form": ("shifted QMR, real Lanczos basis, requested rows" if qmr else
+                            "projected rows (three-term seed)" if projected else "full x"),
                    "autotuned": tuned is not None},
         "converged_pairs": good, "pairs": int(status.size),
         "outer_iterations": {"mean": float(stats[:, 0].mean()), "max": int(stats[:, 0].max())},
@@ -375,7 +403,8 @@ def main():
         "fallback_iterations": int(stats[:, 7].sum()),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_scocg (persistent solver)", "kernel_ms": kernel_s * 1e3,
+                     "kernel": "k_sqmr (persistent solver)" if qmr else "k_scocg (persistent solver)",
+                     "kernel_ms": kernel_s * 1e3,
                      "algorithmic_bytes": alg},
     }
     w = np.zeros(prob.nshift)
@@ -391,14 +420,15 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     ms_int = e0.elapsed_time(e1)
-    int_bytes = plan.out_count * prob.nshift * 16 + plan.out_count * 8 + prob.nrhs * prob.nshift * 8
+    int_bytes = plan.out_count * 16 + (plan.out_count // prob.nshift) * 8 + prob.nrhs * prob.nshift * 8
     out["energy_integration"] = {"ms": ms_int, "bytes": int_bytes, "GB/s": int_bytes / (ms_int * 1e-3) / 1e9,
                                  "what": "density-matrix rows and local DOS from the computed G (trapezoid, "
                                          "mu = 0, kT = 0.1)"}
     if not args.no_cpu_baseline:
         workers = max(1, min(16, os.cpu_count() or 1))
         print(f"[bench] cpu baseline: oracle on {workers} processes ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(prob, stats, args.cpu_rhs, args.cpu_iters, workers, projected)
+        out["cpu_baseline"] = cpu_baseline(prob, stats, args.cpu_rhs, args.cpu_iters, workers,
+                                           "qmr" if qmr else projected)
     print(json.dumps(out), flush=True)
 
 

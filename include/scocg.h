@@ -64,6 +64,8 @@ typedef int32_t scocg_status;
 #define SCOCG_FP32_BF16   2  /* as SCOCG_FP32 but blocks stored as bfloat16 */
 
 /* ---- output modes --------------------------------------------------------- */
+#define SCOCG_METHOD_COCG 0
+#define SCOCG_METHOD_QMR 1
 #define SCOCG_OUT_SELECTED_G  0  /* G_ij for the rows i listed per RHS */
 #define SCOCG_OUT_FULL_X      1  /* the whole x_j(z_k) (cluster-local order) */
 
@@ -168,11 +170,19 @@ typedef struct {
                                requested rows and run the seed in the three-term form
                                (per-shift work O(rows) instead of O(M_j); no audit,
                                resid is the recursive estimate).  Default 1. */
+    int32_t method;         /* SCOCG_METHOD_COCG (default): generalized shifted COCG
+                               with seed switching (Sec. 3, item (i)).
+                               SCOCG_METHOD_QMR: generalized shifted QMR (Sec. 3,
+                               item (ii)) over the real S-Lanczos basis that real H,
+                               S and b = e_j share across all shifts; FP64 with
+                               SELECTED_G output only (E_UNSUPPORTED otherwise);
+                               resid is the quasi-residual bound of the true
+                               residual, iters the step at which it fell below tol. */
 } scocg_options;
 
 /* Defaults: tol 1e-10, maxiter 0, FP64, replace_every 0, inner_maxiter 1000,
  * inner_tol 1e-13, inner_tol_lo 1e-6, seed_index -1, threads 0, slots 0, audit 1,
- * projected 1. */
+ * projected 1, method COCG. */
 void scocg_options_default(scocg_options* opt);
 
 /* ---- right-hand sides ----------------------------------------------------- */
@@ -227,7 +237,8 @@ int64_t scocg_plan_out_count(const scocg_plan* plan);
  * Launch shape of a plan, host int64[SCOCG_NINFO]: [0] resident workgroups,
  * [1] threads per workgroup, [2] padded rows per workgroup slot, [3] bytes of
  * one slot, [4] initial seed index, [5] LDS bytes per workgroup,
- * [6] precision, [7] bit 0: every RHS uses the whole system; bit 1: projected.
+ * [6] precision, [7] bit 0: every RHS uses the whole system; bit 1: projected;
+ * bit 2: the QMR method.
  */
 #define SCOCG_NINFO 8
 scocg_status scocg_plan_info(const scocg_plan* plan, int64_t* info);

@@ -22,6 +22,7 @@ E_ARG, E_SHAPE, E_NOT_SYMMETRIC, E_DEVICE, E_NOMEM, E_UNSUPPORTED = -1, -2, -3, 
 CONVERGED, MAXITER, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 FP64, FP32, FP32_BF16 = 0, 1, 2
 OUT_SELECTED_G, OUT_FULL_X = 0, 1
+METHOD_COCG, METHOD_QMR = 0, 1
 NSTAT = 8
 STAT_NAMES = ("outer", "sum_upd", "inner", "switches", "M", "blocks", "replacements", "fallback")
 
@@ -50,7 +51,7 @@ class scocg_options(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int32), ("precision", C.c_int32),
                 ("replace_every", C.c_int32), ("inner_maxiter", C.c_int32), ("inner_tol", C.c_double),
                 ("inner_tol_lo", C.c_double), ("seed_index", C.c_int32), ("threads", C.c_int32),
-                ("slots", C.c_int32), ("audit", C.c_int32), ("projected", C.c_int32)]
+                ("slots", C.c_int32), ("audit", C.c_int32), ("projected", C.c_int32), ("method", C.c_int32)]
 
 
 class scocg_rhs_spec(C.Structure):

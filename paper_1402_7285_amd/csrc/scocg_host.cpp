@@ -110,6 +110,7 @@ struct scocg_plan {
     int32_t K = 0, nrhs = 0, seed0 = 0;
     int nt = 512, slots = 0, prec = 0;
     bool proj = false;        // projected (requested rows only) FP64 solve
+    bool qmr = false;         // shifted QMR over the real S-Lanczos basis
     int64_t nIp = 0;
     int64_t Mp = 0, slot_bytes = 0, out_count = 0;
     std::vector<int64_t> out_off;
@@ -480,6 +481,7 @@ extern "C" void scocg_options_default(scocg_options* o) {
     o->slots = 0;
     o->audit = 1;
     o->projected = 1;
+    o->method = SCOCG_METHOD_COCG;
 }
 
 // Initial seed: smallest |Im z|, then Re z closest to the median of Re z
@@ -754,7 +756,22 @@ extern "C" scocg_status scocg_plan_create(scocg_problem* P, const scocg_options*
     pl->nt = opt.threads ? opt.threads : 512;
     pl->Mp = std::max<int64_t>(64, (hm.maxM + 63) / 64 * 64);
     pl->proj = opt.projected && opt.precision == SCOCG_FP64 && !(spec && spec->out_mode == SCOCG_OUT_FULL_X);
-    if (pl->proj) {
+    pl->qmr = opt.method == SCOCG_METHOD_QMR;
+    if (opt.method != SCOCG_METHOD_COCG && opt.method != SCOCG_METHOD_QMR) {
+        scocg_plan_free(pl);
+        return fail(SCOCG_E_ARG, "unknown method %d", opt.method);
+    }
+    if (pl->qmr && (opt.precision != SCOCG_FP64 || (spec && spec->out_mode == SCOCG_OUT_FULL_X))) {
+        scocg_plan_free(pl);
+        return fail(SCOCG_E_UNSUPPORTED, "the QMR method runs in FP64 with SELECTED_G output");
+    }
+    if (pl->qmr) {
+        int64_t maxout = 1;
+        for (const auto& r : hm.rhs) maxout = std::max<int64_t>(maxout, r.nout);
+        pl->nIp = (maxout + 63) / 64 * 64;
+        pl->slot_bytes = scocg::qmr_slot_bytes(nshift, pl->Mp, pl->nIp);
+        pl->proj = false;
+    } else if (pl->proj) {
         int64_t maxout = 1;
         for (const auto& r : hm.rhs) maxout = std::max<int64_t>(maxout, r.nout);
         pl->nIp = (maxout + 63) / 64 * 64;
@@ -766,7 +783,7 @@ extern "C" scocg_status scocg_plan_create(scocg_problem* P, const scocg_options*
     auto bail = [&](scocg_status e) { scocg_plan_free(pl); return e; };
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess || cus <= 0) cus = 256;
-    const size_t lds = scocg::solver_lds_bytes(nshift, pl->nt);
+    const size_t lds = pl->qmr ? scocg::qmr_lds_bytes(nshift, pl->nt) : scocg::solver_lds_bytes(nshift, pl->nt);
     if (lds > 160 * 1024) return bail(fail(SCOCG_E_UNSUPPORTED, "too many shifts for LDS"));
     int per_cu = std::max(1, 2048 / pl->nt);
     per_cu = std::min<int>(per_cu, (int)std::max<size_t>(1, (160 * 1024) / lds));
@@ -824,9 +841,9 @@ extern "C" scocg_status scocg_plan_info(const scocg_plan* pl, int64_t* info) {
     info[2] = pl->Mp;
     info[3] = pl->slot_bytes;
     info[4] = pl->seed0;
-    info[5] = (int64_t)scocg::solver_lds_bytes(pl->K, pl->nt);
+    info[5] = (int64_t)(pl->qmr ? scocg::qmr_lds_bytes(pl->K, pl->nt) : scocg::solver_lds_bytes(pl->K, pl->nt));
     info[6] = pl->prec;
-    info[7] = (pl->global ? 1 : 0) | (pl->proj ? 2 : 0);
+    info[7] = (pl->global ? 1 : 0) | (pl->proj ? 2 : 0) | (pl->qmr ? 4 : 0);
     return SCOCG_OK;
 }
 
@@ -896,7 +913,8 @@ extern "C" scocg_status scocg_plan_run(scocg_plan* pl, void* stream, scocg_z* ou
     KParams k = make_kparams(pl, out, iters, status, resid);
     (void)hipGetLastError();   // drop any error another caller left on this thread
     HIP_TRY(scocg::launch_fill_i32(pl->dqueue, 0, 1, st));
-    HIP_TRY(scocg::launch_solver(k, P->bd, pl->proj ? 3 : pl->prec, !P->has_S, pl->nt, pl->slots, st));
+    if (pl->qmr) HIP_TRY(scocg::launch_qmr(k, P->bd, !P->has_S, pl->nt, pl->slots, st));
+    else HIP_TRY(scocg::launch_solver(k, P->bd, pl->proj ? 3 : pl->prec, !P->has_S, pl->nt, pl->slots, st));
     return SCOCG_OK;
 }
 

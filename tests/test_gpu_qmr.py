@@ -1,0 +1,77 @@
+"""GPU shifted QMR (method = QMR) against the QMR oracle on the same inputs,
+and its argument rules.  The parity rule is the projected COCG form's: per
+(RHS, shift) relative difference <= 1e-8 with equal status, iteration
+counts within 25%, else both inside the a-priori bound of the dense
+solution."""
+import numpy as np
+import pytest
+
+from oracle import local_system, sqmr
+from synth import bsr_to_scipy, make_config, make_problem
+from tests.parity import compare_rhs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B(gpu_lib):
+    from paper_1402_7285_amd import binding
+    return binding
+
+
+def _plan(B, prob, **opt):
+    P = B.Problem(prob.H, prob.S)
+    kw = dict(out_ptr=prob.out_ptr, out_rows=prob.out_rows)
+    if prob.cluster_ptr is not None:
+        kw.update(cluster_ptr=prob.cluster_ptr, cluster_atoms=prob.cluster_atoms)
+    opt.setdefault("tol", prob.tol)
+    return P, B.Plan(P, prob.shifts, prob.rhs, method=B.METHOD_QMR, **kw, **opt)
+
+
+CASES = {
+    "cfg0_S=I": lambda: make_config(0, nrhs=4),
+    "sc4_generalized": lambda: make_problem(name="sc4-gen", lattice="sc", L=4, bdim=4, s_scale=0.03, K=16, eta=0.05,
+                                            nrhs=4, seed_key=(5, 5, 5)),
+    "fcc3_clusters": lambda: make_problem(name="fcc3-clusters", lattice="fcc", L=3, bdim=9, hop=(0.0, 0.5),
+                                          s_scale=0.03, K=12, eta=0.05, nrhs=6, radius=(1.0, 1.6),
+                                          seed_key=(6, 6, 6)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("threads", [512, 1024])
+def test_qmr_parity(B, case, threads):
+    prob = CASES[case]()
+    P, plan = _plan(B, prob, threads=threads)
+    assert plan.info["global"] & 4
+    r = plan.solve()
+    Hcsr = bsr_to_scipy(prob.H)
+    Scsr = bsr_to_scipy(prob.S) if prob.S is not None else None
+    worst, report = 0.0, []
+    for j in range(prob.nrhs):
+        Hc, Sc, loc, orb = local_system(prob, j, Hcsr, Scsr)
+        b = np.zeros(orb.size)
+        b[loc] = 1.0
+        pos = np.searchsorted(orb, prob.outs(j))
+        res = sqmr(Hc, Sc, prob.shifts, b, prob.tol, rows=pos)
+        worst = max(worst, compare_rhs(r["G"][j], r["iters"][j], r["status"][j], res, Hc, Sc, prob.shifts,
+                                       b.astype(np.complex128), prob.tol, rows=pos, iter_frac=0.25, report=report,
+                                       tag=f"rhs {j}"))
+        assert abs(int(r["stats"][j][0]) - res.n_outer) <= max(3, 0.25 * res.n_outer)
+        assert r["stats"][j][3] == 0          # no seed switches in the Lanczos form
+    print(f"[qmr] {case} threads={threads}: worst rel err {worst:.2e}; shifts with other counts {len(report)}",
+          flush=True)
+
+
+def test_qmr_argument_rules(B):
+    prob = make_config(0, nrhs=2)
+    with pytest.raises(B.ScocgError) as ei:
+        _plan(B, prob, full_x=True)
+    assert ei.value.code == B.E_UNSUPPORTED
+    with pytest.raises(B.ScocgError) as ei:
+        _plan(B, prob, precision=B.FP32)
+    assert ei.value.code == B.E_UNSUPPORTED
+    with pytest.raises(B.ScocgError) as ei:
+        P = B.Problem(prob.H, prob.S)
+        B.Plan(P, prob.shifts, prob.rhs, method=7, out_ptr=prob.out_ptr, out_rows=prob.out_rows)
+    assert ei.value.code == B.E_ARG
