@@ -39,6 +39,8 @@ WORKLOADS = {
                        "matrices, 256 shifts + 0.01i"),
 }
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+METHODS = {"cocg": 0, "qmr": 1, "cocg-lanczos": 2}
+_FORM_NAMES = {"qmr": "shifted QMR, real Lanczos basis", "lanczos": "COCG iterates on the real Lanczos basis"}
 
 
 def algorithmic_bytes_qmr(stats, nout, bd, has_S, w_share):
@@ -100,7 +102,7 @@ def cpu_baseline(prob, gpu_stats, n_rhs_sample, iters_sample, workers, projected
     rate = prob.nshift * min(workers, len(idx)) / t_rhs
     return dict(value=rate, unit="solves/s", cores=int(min(workers, len(idx))), kind="oracle",
                 sample=f"{len(idx)} RHS x {iters_sample} outer iterations of the same workload "
-                       f"({'shifted QMR, real Lanczos basis' if projected == 'qmr' else 'projected rows, three-term form' if projected else 'full x'}), one RHS per "
+                       f"({_FORM_NAMES.get(projected, 'projected rows, three-term form' if projected else 'full x')}), one RHS per "
                        f"process ({workers} processes, 1 BLAS thread each); t/iteration {t_iter * 1e3:.1f} ms "
                        f"x mean outer iterations {mean_outer:.0f} (GPU run) = {t_rhs:.0f} s per RHS of "
                        f"{prob.nshift} shifts; wall {wall:.1f} s")
@@ -109,12 +111,13 @@ def cpu_baseline(prob, gpu_stats, n_rhs_sample, iters_sample, workers, projected
 def _cpu_worker(args):
     prob, j, iters, projected = args
     qmr = projected == "qmr"
+    lanczos = projected == "lanczos"
     try:
         from threadpoolctl import threadpool_limits
         threadpool_limits(1)
     except Exception:
         pass
-    from oracle import local_system, scocg, scocg_projected, sqmr
+    from oracle import local_system, scocg, scocg_lanczos, scocg_projected, sqmr
     from synth import bsr_to_scipy
     H = bsr_to_scipy(prob.H)
     S = bsr_to_scipy(prob.S) if prob.S is not None else None
@@ -122,9 +125,10 @@ def _cpu_worker(args):
     b = np.zeros(orb.size, dtype=np.complex128)
     b[loc] = 1.0
     t0 = time.perf_counter()
-    if qmr:
+    if qmr or lanczos:
         rows = np.searchsorted(orb, prob.outs(j))
-        res = sqmr(Hc, Sc, prob.shifts, b.real, 1e-6, rows=rows, maxiter=iters)
+        fn = sqmr if qmr else scocg_lanczos
+        res = fn(Hc, Sc, prob.shifts, b.real, 1e-6, rows=rows, maxiter=iters)
     elif projected:
         rows = np.searchsorted(orb, prob.outs(j))
         res = scocg_projected(Hc, Sc, prob.shifts, b, rows, 1e-6, maxiter=iters)
@@ -178,6 +182,74 @@ def plain_baseline(B, P, prob, args, kw):
            "form": "full x, FP64, one workgroup per RHS, all RHS concurrent", "threads": plan.info["threads"],
            "slots": plan.info["slots"]}
     print(json.dumps(out), flush=True)
+
+
+def measure_form(B, P, prob, kw, args, method, stream):
+    """Autotune (unless the launch shape is given), build the plan, run the
+    warm-up and the timed steps of one form of the solve; returns the plan,
+    its buffers, the solves/s and the report fields (iterations, roofline)."""
+    import torch
+    threads, slots, tuned = args.threads, args.slots, None
+    if not args.no_autotune and not args.threads and not args.slots:
+        tuned = B.autotune(P, prob.shifts, prob.rhs, probe_iters=50,
+                           cache_path=os.path.join(ROOT, "paper_1402_7285_amd", "autotune_cache.json"),
+                           key_extra=f"{args.workload}|{args.nrhs}", tol=args.tol, precision=PREC[args.precision],
+                           projected=args.projected, method=METHODS[method], **kw)
+        threads, slots = tuned["threads"], tuned["slots"]
+        print(f"[bench] {method}: autotuned {tuned}", file=sys.stderr, flush=True)
+    plan = B.Plan(P, prob.shifts, prob.rhs, tol=args.tol, precision=PREC[args.precision], audit=1,
+                  threads=threads, slots=slots, projected=args.projected, maxiter=args.maxiter,
+                  method=METHODS[method], **kw)
+    projected = bool(plan.info["global"] & 2)
+    qmr = bool(plan.info["global"] & 4)
+    gal = bool(plan.info["global"] & 8)
+    bufs = plan.alloc_outputs()
+    for w in range(args.warmup):
+        plan.run(bufs, stream)
+        torch.cuda.synchronize()
+        print(f"[bench] {method}: warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        plan.run(bufs, stream)
+        ev[i][1].record(stream)
+        torch.cuda.synchronize()
+        print(f"[bench] {method}: step {i + 1}/{args.steps}: {ev[i][0].elapsed_time(ev[i][1]) / 1e3:.2f} s",
+              file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    kernel_s = float(np.mean([a.elapsed_time(b) for a, b in ev])) / 1e3
+    status = bufs["status"].cpu().numpy()
+    resid = bufs["resid"].cpu().numpy()
+    good = int(np.sum((status == 0) & (resid <= 1e-6)))
+    stats = plan.stats()
+    ms_per_step = wall / args.steps * 1e3
+    nout = np.diff(prob.out_ptr)
+    w_share = min(plan.info["slots"], prob.nrhs) if prob.cluster_ptr is None else 1
+    if qmr:
+        alg = algorithmic_bytes_qmr(stats, nout, prob.bdim, prob.S is not None, w_share)
+    else:
+        alg = algorithmic_bytes(stats, nout, prob.nshift, prob.bdim, prob.S is not None, PREC[args.precision],
+                                projected, w_share, True)
+    achieved = alg / kernel_s / 1e9
+    form_key = "lanczos" if gal else "qmr" if qmr else ("proj" if projected else "full")
+    report = {
+        "converged_pairs": good, "pairs": int(status.size),
+        "outer_iterations": {"mean": float(stats[:, 0].mean()), "max": int(stats[:, 0].max())},
+        "inner_per_outer": float(stats[:, 2].sum() / max(1, stats[:, 0].sum())),
+        "fallback_iterations": int(stats[:, 7].sum()),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args, form_key),
+                     "kernel": "k_sqmr (persistent solver)" if qmr else "k_scocg (persistent solver)",
+                     "kernel_ms": kernel_s * 1e3, "algorithmic_bytes": alg},
+    }
+    form = ("COCG iterates on the real Lanczos basis, requested rows" if gal else
+            "shifted QMR, real Lanczos basis, requested rows" if qmr else
+            "seed-switching COCG, projected rows (three-term seed)" if projected else "seed-switching COCG, full x")
+    cpu_form = "lanczos" if gal else "qmr" if qmr else projected
+    return dict(plan=plan, bufs=bufs, value=good / (ms_per_step / 1e3), ms_per_step=ms_per_step, stats=stats,
+                report=report, form=form, cpu_form=cpu_form, autotuned=tuned is not None)
 
 
 def binning_ab(B, args):
@@ -263,26 +335,35 @@ def binning_ab(B, args):
     print(json.dumps(out), flush=True)
 
 
-def _kernel_source_hash():
+KERNEL_SOURCES = {
+    "proj": ("scocg_kernels.hip", "scocg_device.hpp", "scocg_params.hpp"),
+    "full": ("scocg_kernels.hip", "scocg_device.hpp", "scocg_params.hpp"),
+    "qmr": ("qmr_kernels.hip", "scocg_device.hpp", "scocg_params.hpp"),
+    "lanczos": ("qmr_kernels.hip", "scocg_device.hpp", "scocg_params.hpp"),
+}
+
+
+def _kernel_source_hash(form="proj"):
     import hashlib
     h = hashlib.sha256()
-    for f in ("scocg_kernels.hip", "scocg_device.hpp", "scocg_params.hpp"):
+    for f in KERNEL_SOURCES[form]:
         with open(os.path.join(ROOT, "paper_1402_7285_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(args, projected):
+def measured_traffic(args, form):
     """HBM bytes per launch from the committed rocprofv3 counter summary of
-    this workload (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading),
-    or None if there is none or the kernel sources changed since."""
-    key = f"{args.workload}_{args.precision}_{'qmr' if args.method == 'qmr' else 'proj' if projected else 'full'}"
+    this workload and form (FETCH_SIZE + WRITE_SIZE, scaled by a plain
+    copy's reading), or None if there is none or the kernel sources changed
+    since."""
+    key = f"{args.workload}_{args.precision}_{form}"
     path = os.path.join(ROOT, "profiles", f"k_scocg_{key}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_source_hash") != _kernel_source_hash():
+    if t.get("kernel_source_hash") != _kernel_source_hash(form):
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -302,10 +383,13 @@ def main():
     ap.add_argument("--cpu-rhs", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--projected", type=int, default=1, help="FP64 SELECTED_G: rows-only solve (default 1)")
-    ap.add_argument("--method", default="cocg", choices=["cocg", "qmr"],
-                    help="cocg: shifted COCG with seed switching; qmr: shifted QMR over the real Lanczos basis")
+    ap.add_argument("--method", default="cocg-lanczos", choices=["cocg", "qmr", "cocg-lanczos"],
+                    help="cocg: shifted COCG with seed switching; qmr: shifted QMR over the real Lanczos basis; "
+                         "cocg-lanczos: the COCG iterates on that basis")
     ap.add_argument("--copy-calib", type=int, default=0, help="only run a device copy of this many bytes")
     ap.add_argument("--no-autotune", action="store_true", help="use --threads/--slots as given")
+    ap.add_argument("--no-companion", action="store_true",
+                    help="do not also time the seed-switching COCG form when --method is another form")
     ap.add_argument("--plain", type=int, default=0,
                     help="measure FP64 plain instead: full x, one RHS at a time, on this many RHS")
     ap.add_argument("--binning", default="",
@@ -340,73 +424,27 @@ def main():
         kw.update(cluster_ptr=prob.cluster_ptr, cluster_atoms=prob.cluster_atoms)
     if args.plain:
         return plain_baseline(B, P, prob, args, kw)
-    tuned = None
-    if not args.no_autotune and not args.threads and not args.slots:
-        tuned = B.autotune(P, prob.shifts, prob.rhs, probe_iters=50,
-                           cache_path=os.path.join(ROOT, "paper_1402_7285_amd", "autotune_cache.json"),
-                           key_extra=f"{args.workload}|{args.nrhs}", tol=args.tol, precision=PREC[args.precision],
-                           projected=args.projected, method=int(args.method == "qmr"), **kw)
-        args.threads, args.slots = tuned["threads"], tuned["slots"]
-        print(f"[bench] autotuned: {tuned}", file=sys.stderr, flush=True)
-    plan = B.Plan(P, prob.shifts, prob.rhs, tol=args.tol, precision=PREC[args.precision], audit=1,
-                  threads=args.threads, slots=args.slots, projected=args.projected, maxiter=args.maxiter,
-                  method=int(args.method == "qmr"), **kw)
-    projected = bool(plan.info["global"] & 2)
-    qmr = bool(plan.info["global"] & 4)
-    bufs = plan.alloc_outputs()
     stream = torch.cuda.current_stream()
-    for w in range(args.warmup):
-        plan.run(bufs, stream)
-        torch.cuda.synchronize()
-        print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ev[i][0].record(stream)
-        plan.run(bufs, stream)
-        ev[i][1].record(stream)
-        torch.cuda.synchronize()
-        print(f"[bench] step {i + 1}/{args.steps}: {ev[i][0].elapsed_time(ev[i][1]) / 1e3:.2f} s",
-              file=sys.stderr, flush=True)
-    wall = time.perf_counter() - t0
-    kernel_s = float(np.mean([a.elapsed_time(b) for a, b in ev])) / 1e3
-    status = bufs["status"].cpu().numpy()
-    resid = bufs["resid"].cpu().numpy()
-    good = int(np.sum((status == 0) & (resid <= 1e-6)))
-    stats = plan.stats()
-    ms_per_step = wall / args.steps * 1e3
-    value = good / (ms_per_step / 1e3)
-    nout = np.diff(prob.out_ptr)
-    w_share = min(plan.info["slots"], prob.nrhs) if prob.cluster_ptr is None else 1
-    if qmr:
-        alg = algorithmic_bytes_qmr(stats, nout, prob.bdim, prob.S is not None, w_share)
-    else:
-        alg = algorithmic_bytes(stats, nout, prob.nshift, prob.bdim, prob.S is not None, PREC[args.precision],
-                                projected, w_share, True)
-    achieved = alg / kernel_s / 1e9
-    traffic = measured_traffic(args, projected)
+    r = measure_form(B, P, prob, kw, args, args.method, stream)
+    plan, bufs = r["plan"], r["bufs"]
     out = {
-        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": r["value"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": {"fp64": "c128", "fp32": "c64", "bf16": "c64/bf16"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {wl['desc']}", "nrhs": prob.nrhs, "shifts": prob.nshift,
                    "M": prob.M, "tol": args.tol, "precision": args.precision, "batched": "persistent",
-                   "slots": plan.info["slots"], "threads": plan.info["threads"],
-                   "form": ("shifted QMR, real Lanczos basis, requested rows" if qmr else
-                            "projected rows (three-term seed)" if projected else "full x"),
-                   "autotuned": tuned is not None},
-        "converged_pairs": good, "pairs": int(status.size),
-        "outer_iterations": {"mean": float(stats[:, 0].mean()), "max": int(stats[:, 0].max())},
-        "inner_per_outer": float(stats[:, 2].sum() / max(1, stats[:, 0].sum())),
-        "fallback_iterations": int(stats[:, 7].sum()),
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_sqmr (persistent solver)" if qmr else "k_scocg (persistent solver)",
-                     "kernel_ms": kernel_s * 1e3,
-                     "algorithmic_bytes": alg},
+                   "slots": plan.info["slots"], "threads": plan.info["threads"], "form": r["form"],
+                   "autotuned": r["autotuned"]},
+        **r["report"],
     }
+    if args.method != "cocg" and not args.no_companion:
+        # the seed-switching form of the same method, timed in the same run
+        c = measure_form(B, P, prob, kw, args, "cocg", stream)
+        out["seed_switching_form"] = {"form": c["form"], "value": c["value"], "ms_per_step": c["ms_per_step"],
+                                      "threads": c["plan"].info["threads"], "slots": c["plan"].info["slots"],
+                                      **c["report"]}
+        del c
     w = np.zeros(prob.nshift)
     if prob.nshift > 1:
         dE = np.diff(prob.shifts.real)
@@ -427,8 +465,7 @@ def main():
     if not args.no_cpu_baseline:
         workers = max(1, min(16, os.cpu_count() or 1))
         print(f"[bench] cpu baseline: oracle on {workers} processes ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(prob, stats, args.cpu_rhs, args.cpu_iters, workers,
-                                           "qmr" if qmr else projected)
+        out["cpu_baseline"] = cpu_baseline(prob, r["stats"], args.cpu_rhs, args.cpu_iters, workers, r["cpu_form"])
     print(json.dumps(out), flush=True)
 
 

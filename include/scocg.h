@@ -66,6 +66,7 @@ typedef int32_t scocg_status;
 /* ---- output modes --------------------------------------------------------- */
 #define SCOCG_METHOD_COCG 0
 #define SCOCG_METHOD_QMR 1
+#define SCOCG_METHOD_COCG_LANCZOS 2
 #define SCOCG_OUT_SELECTED_G  0  /* G_ij for the rows i listed per RHS */
 #define SCOCG_OUT_FULL_X      1  /* the whole x_j(z_k) (cluster-local order) */
 
@@ -177,7 +178,13 @@ typedef struct {
                                S and b = e_j share across all shifts; FP64 with
                                SELECTED_G output only (E_UNSUPPORTED otherwise);
                                resid is the quasi-residual bound of the true
-                               residual, iters the step at which it fell below tol. */
+                               residual, iters the step at which it fell below tol.
+                               SCOCG_METHOD_COCG_LANCZOS: the shifted COCG iterates
+                               (those of the default method, in exact arithmetic)
+                               computed on that real basis by an LDL^T of each
+                               shift's tridiagonal, with no seed; resid is the
+                               residual norm |zeta_n| ||t|| the recurrences give.
+                               Same restrictions as QMR. */
 } scocg_options;
 
 /* Defaults: tol 1e-10, maxiter 0, FP64, replace_every 0, inner_maxiter 1000,
@@ -238,7 +245,7 @@ int64_t scocg_plan_out_count(const scocg_plan* plan);
  * [1] threads per workgroup, [2] padded rows per workgroup slot, [3] bytes of
  * one slot, [4] initial seed index, [5] LDS bytes per workgroup,
  * [6] precision, [7] bit 0: every RHS uses the whole system; bit 1: projected;
- * bit 2: the QMR method.
+ * bit 2: a real Lanczos-basis method; bit 3: its COCG (Galerkin) iterates.
  */
 #define SCOCG_NINFO 8
 scocg_status scocg_plan_info(const scocg_plan* plan, int64_t* info);

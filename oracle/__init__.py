@@ -12,4 +12,4 @@ from .scocg import (  # noqa: F401
 )
 from .dense import dense_solve, green_eig, true_residual  # noqa: F401
 from . import mlp, features, integrate  # noqa: F401
-from .qmr import sqmr  # noqa: F401
+from .qmr import scocg_lanczos, sqmr  # noqa: F401

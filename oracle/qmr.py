@@ -143,3 +143,96 @@ def sqmr(H, S, z, b, tol: float, rows=None, maxiter: Optional[int] = None, inner
         v, w = q / beta_next, t / beta_next
         beta = beta_next
     return ScocgResult(x, iters, status, resid, n_outer, inner_total, [])
+
+
+def scocg_lanczos(H, S, z, b, tol: float, rows=None, maxiter: Optional[int] = None, inner_tol: float = 1e-13,
+                  inner_maxiter: int = 1000) -> ScocgResult:
+    """The shifted COCG iterates of every shift, computed on the real
+    S-Lanczos basis of the module docstring (real H, S, b).
+
+    With a real basis the unconjugated bilinear form u^T S v of COCG is the
+    S-inner product, so COCG's Galerkin condition V_n^T (b - (z_k S - H) x) = 0
+    makes x_k = V_n y_k with (z_k I - T_n) y_k = beta_0 e_1: the same iterates
+    as the seed-switching form in exact arithmetic.  Each shift factors its
+    complex symmetric tridiagonal z_k I - T_n as L D L^T, one pivot per
+    iteration (delta_n = z_k - alpha_n - beta_n^2 / delta_{n-1}), with
+    p_n = v_n + (beta_n / delta_{n-1}) p_{n-1}, zeta_n = g_n / delta_n,
+    g_n = (beta_n / delta_{n-1}) g_{n-1}, x_k += zeta_n p_n.  The residual is
+    b - (z_k S - H) x_k = zeta_n t (t = beta_{n+1} w_{n+1}), so its norm
+    |zeta_n| ||t|| is known exactly; shift k stops when it is below tol ||b||.
+    """
+    b = np.asarray(b)
+    if np.iscomplexobj(b):
+        if np.any(b.imag != 0):
+            raise ValueError("the real Lanczos form needs a real right-hand side")
+        b = b.real
+    b = b.astype(np.float64)
+    z = np.asarray(z, dtype=np.complex128)
+    M, K = b.size, z.size
+    rows = np.arange(M) if rows is None else np.asarray(rows)
+    maxiter = max(1000, 4 * M) if maxiter is None else maxiter
+    nb = np.linalg.norm(b)
+    inner_total = 0
+
+    def s_solve(t):
+        nonlocal inner_total
+        if S is None:
+            return t.copy()
+        q, it = inner_cg(S, t, inner_tol, inner_maxiter)
+        inner_total += it
+        return q
+
+    x = np.zeros((rows.size, K), dtype=np.complex128)
+    iters = np.full(K, -1, dtype=np.int64)
+    status = np.full(K, MAXITER, dtype=np.int8)
+    resid = np.full(K, np.inf)
+    if nb == 0.0:
+        return ScocgResult(x, np.zeros(K, np.int64), np.zeros(K, np.int8), np.zeros(K), 0, 0, [])
+    q0 = s_solve(b)
+    beta0 = np.sqrt(b @ q0)
+    v, w = q0 / beta0, b / beta0
+    w_prev = np.zeros(M)
+    beta = 0.0
+    delta = np.ones(K, dtype=np.complex128)       # previous pivot (unused at n = 0)
+    g = np.full(K, beta0, dtype=np.complex128)
+    p = np.zeros((rows.size, K), dtype=np.complex128)
+    done = np.zeros(K, dtype=bool)
+    n_outer = 0
+    for n in range(maxiter):
+        n_outer = n + 1
+        u = H @ v
+        alpha = v @ u
+        t = u - alpha * w - beta * w_prev
+        q = s_solve(t)
+        qt = q @ t
+        if not np.isfinite(qt):
+            status[~done], done[:] = NONFINITE, True
+            break
+        if qt < 0.0:
+            status[~done], done[:] = BREAKDOWN, True
+            break
+        beta_next = np.sqrt(qt)
+        tnorm = np.linalg.norm(t)
+        vr = v[rows]
+        for k in range(K):
+            if done[k]:
+                continue
+            c = 0.0 if n == 0 else beta / delta[k]
+            dn = z[k] - alpha - (0.0 if n == 0 else beta * beta / delta[k])
+            if dn == 0.0:
+                status[k], done[k] = BREAKDOWN, True
+                continue
+            g[k] = beta0 if n == 0 else c * g[k]
+            zeta = g[k] / dn
+            p[:, k] = vr + c * p[:, k]
+            x[:, k] += zeta * p[:, k]
+            delta[k] = dn
+            resid[k] = abs(zeta) * tnorm / nb
+            if resid[k] < tol or beta_next == 0.0:
+                status[k], done[k], iters[k] = CONVERGED, True, n + 1
+        if done.all() or beta_next == 0.0:
+            break
+        w_prev = w
+        v, w = q / beta_next, t / beta_next
+        beta = beta_next
+    return ScocgResult(x, iters, status, resid, n_outer, inner_total, [])

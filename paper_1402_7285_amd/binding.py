@@ -22,7 +22,7 @@ E_ARG, E_SHAPE, E_NOT_SYMMETRIC, E_DEVICE, E_NOMEM, E_UNSUPPORTED = -1, -2, -3, 
 CONVERGED, MAXITER, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 FP64, FP32, FP32_BF16 = 0, 1, 2
 OUT_SELECTED_G, OUT_FULL_X = 0, 1
-METHOD_COCG, METHOD_QMR = 0, 1
+METHOD_COCG, METHOD_QMR, METHOD_COCG_LANCZOS = 0, 1, 2
 NSTAT = 8
 STAT_NAMES = ("outer", "sum_upd", "inner", "switches", "M", "blocks", "replacements", "fallback")
 

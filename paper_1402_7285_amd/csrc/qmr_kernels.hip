@@ -18,6 +18,17 @@
 // and no seed switching: the Lanczos process does not depend on the shifts.
 // All long-vector traffic is real (8 bytes per element), half that of the
 // complex COCG seed process.
+//
+// The same basis also gives the shifted COCG iterates themselves (GAL): with
+// a real basis COCG's unconjugated form u^T S v is the S-inner product, so
+// COCG's Galerkin condition makes x_k = V_n y_k with (z_k I - T_n) y_k =
+// beta_0 e_1.  Each shift factors z_k I - T_n as L D L^T, one pivot per
+// iteration, delta_n = z_k - alpha_n - beta_n^2 / delta_{n-1}, and updates
+// p_n = v_n + (beta_n / delta_{n-1}) p_{n-1}, x_k += zeta_n p_n with
+// zeta_n = g_n / delta_n, g_n = (beta_n / delta_{n-1}) g_{n-1}; its residual
+// is zeta_n t (t = beta_{n+1} w_{n+1}), whose norm |zeta_n| ||t|| is the
+// stopping test.  Same iterates as the seed-switching COCG in exact
+// arithmetic, without a seed.
 #include <hip/hip_runtime.h>
 
 #include "scocg_device.hpp"
@@ -224,7 +235,7 @@ __host__ __device__ inline int64_t slot_bytes(int K, int64_t Mp, int64_t nIp) {
     return ((8 * Mp) * 8 + 3 * (int64_t)K * nIp * 16 + 255) / 256 * 256;
 }
 
-template <int BD, int NT, bool SID>
+template <int BD, int NT, bool SID, bool GAL>
 __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
     const int tid = threadIdx.x;
     const int K = P.K;
@@ -280,7 +291,7 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
     for (int k = tid; k < K; k += NT) {
         L.c1[k] = 1.0;
         L.c2[k] = 1.0;
-        L.s1[k] = zmk(0.0, 0.0);
+        L.s1[k] = GAL ? zmk(1.0, 0.0) : zmk(0.0, 0.0);    // GAL: previous pivot
         L.s2[k] = zmk(0.0, 0.0);
         L.g[k] = zmk(beta0, 0.0);
         L.done[k] = 0;
@@ -341,8 +352,30 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
         }
         if (beta_next > 0.0) sum_w2 += tt[0] / qt[0];
         const double bscale = sqrt(sum_w2);
-        // ---- per-shift rotations (FP64), one thread per shift
-        for (int k = tid; k < K; k += NT) {
+        // ---- per-shift scalars (FP64), one thread per shift
+        if constexpr (GAL) {
+            for (int k = tid; k < K; k += NT) {
+                if (L.done[k]) continue;
+                const zc zk = zmk(P.z[2 * k], P.z[2 * k + 1]);
+                const zc dprev = L.s1[k];
+                zc c = zmk(0.0, 0.0), dn = zmk(zk.re - alpha, zk.im), gk = zmk(beta0, 0.0);
+                if (n > 0) {
+                    c = zdiv(zmk(beta, 0.0), dprev);
+                    dn = zsub(dn, zmul(zmk(beta, 0.0), c));
+                    gk = zmul(c, L.g[k]);
+                }
+                if (zzero(dn) || !zfinite(dn)) {
+                    L.stat[k] = zfinite(dn) ? ST_BREAKDOWN : ST_NONFINITE;
+                    L.done[k] = 1;
+                    continue;
+                }
+                L.g[k] = gk;
+                L.tau[k] = zdiv(gk, dn);
+                L.e[k] = c;
+                L.s1[k] = dn;
+            }
+        }
+        for (int k = tid; k < K && !GAL; k += NT) {
             if (L.done[k]) continue;
             const zc zk = zmk(P.z[2 * k], P.z[2 * k + 1]);
             const zc a_prev = zmk(-beta, 0.0);
@@ -394,7 +427,19 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
         // ---- d_n = (v_n - e d_{n-2} - f d_{n-1}) / R_nn; x += tau d_n on the requested rows
         double2* Dn2 = (n & 1) ? D1 : D0;      // holds d_{n-2}; receives d_n
         double2* Dn1 = (n & 1) ? D0 : D1;      // holds d_{n-1}
-        for (int idx = tid; idx < nupd * nI; idx += NT) {
+        for (int idx = tid; idx < nupd * nI && GAL; idx += NT) {
+            const int kk = idx / nI, o = idx - kk * nI;
+            const int k = L.upd[kk];
+            const int64_t a = (int64_t)k * nIp + o;
+            const double2 pv = D0[a];
+            const zc c = L.e[k];
+            const zc pn = zmk(v[rows[o]] + c.re * pv.x - c.im * pv.y, c.re * pv.y + c.im * pv.x);
+            D0[a] = make_double2(pn.re, pn.im);
+            const zc tk = L.tau[k];
+            const double2 xv = xI[a];
+            xI[a] = make_double2(xv.x + tk.re * pn.re - tk.im * pn.im, xv.y + tk.re * pn.im + tk.im * pn.re);
+        }
+        for (int idx = tid; idx < nupd * nI && !GAL; idx += NT) {
             const int kk = idx / nI, o = idx - kk * nI;
             const int k = L.upd[kk];
             const int64_t a = (int64_t)k * nIp + o;
@@ -408,9 +453,10 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
             xI[a] = make_double2(xv.x + tk.re * dn.re - tk.im * dn.im, xv.y + tk.re * dn.im + tk.im * dn.re);
         }
         // ---- convergence (bound on the true residual; ||b|| = 1)
+        const double tnorm = sqrt(tt[0]);
         for (int k = tid; k < K; k += NT) {
             if (L.done[k]) continue;
-            const double est = zabs(L.g[k]) * bscale;
+            const double est = GAL ? zabs(L.tau[k]) * tnorm : zabs(L.g[k]) * bscale;
             L.resid[k] = est;
             if (est < P.tol || beta_next == 0.0) {
                 L.done[k] = 1;
@@ -473,7 +519,7 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
     __syncthreads();
 }
 
-template <int BD, int NT, bool SID>
+template <int BD, int NT, bool SID, bool GAL>
 __global__ __launch_bounds__(NT) void k_sqmr(KParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_job;
@@ -488,23 +534,28 @@ __global__ __launch_bounds__(NT) void k_sqmr(KParams P) {
         const int job = s_job;
         __syncthreads();
         if (job >= P.nrhs) break;
-        solve_one<BD, NT, SID>(P, P.order[job], ws, L);
+        solve_one<BD, NT, SID, GAL>(P, P.order[job], ws, L);
     }
 }
 
 template <int BD, int NT>
-static hipError_t launch_nt(const KParams& P, bool sid, int slots, hipStream_t st) {
+static hipError_t launch_nt(const KParams& P, bool sid, bool gal, int slots, hipStream_t st) {
     const size_t lds = lds_bytes(P.K, NT);
-    if (sid) hipLaunchKernelGGL((k_sqmr<BD, NT, true>), dim3(slots), dim3(NT), lds, st, P);
-    else hipLaunchKernelGGL((k_sqmr<BD, NT, false>), dim3(slots), dim3(NT), lds, st, P);
+    if (gal) {
+        if (sid) hipLaunchKernelGGL((k_sqmr<BD, NT, true, true>), dim3(slots), dim3(NT), lds, st, P);
+        else hipLaunchKernelGGL((k_sqmr<BD, NT, false, true>), dim3(slots), dim3(NT), lds, st, P);
+    } else {
+        if (sid) hipLaunchKernelGGL((k_sqmr<BD, NT, true, false>), dim3(slots), dim3(NT), lds, st, P);
+        else hipLaunchKernelGGL((k_sqmr<BD, NT, false, false>), dim3(slots), dim3(NT), lds, st, P);
+    }
     return hipGetLastError();
 }
 
 template <int BD>
-static hipError_t launch_bd(const KParams& P, bool sid, int nt, int slots, hipStream_t st) {
-    if (nt == 256) return launch_nt<BD, 256>(P, sid, slots, st);
-    if (nt == 1024) return launch_nt<BD, 1024>(P, sid, slots, st);
-    return launch_nt<BD, 512>(P, sid, slots, st);
+static hipError_t launch_bd(const KParams& P, bool sid, bool gal, int nt, int slots, hipStream_t st) {
+    if (nt == 256) return launch_nt<BD, 256>(P, sid, gal, slots, st);
+    if (nt == 1024) return launch_nt<BD, 1024>(P, sid, gal, slots, st);
+    return launch_nt<BD, 512>(P, sid, gal, slots, st);
 }
 
 }  // namespace qmr
@@ -513,11 +564,11 @@ size_t qmr_lds_bytes(int K, int nt) { return qmr::lds_bytes(K, nt); }
 
 int64_t qmr_slot_bytes(int K, int64_t Mp, int64_t nIp) { return qmr::slot_bytes(K, Mp, nIp); }
 
-hipError_t launch_qmr(const KParams& P, int bd, bool sid, int nt, int slots, hipStream_t st) {
+hipError_t launch_qmr(const KParams& P, int bd, bool sid, bool gal, int nt, int slots, hipStream_t st) {
     switch (bd) {
-        case 1: return qmr::launch_bd<1>(P, sid, nt, slots, st);
-        case 4: return qmr::launch_bd<4>(P, sid, nt, slots, st);
-        case 9: return qmr::launch_bd<9>(P, sid, nt, slots, st);
+        case 1: return qmr::launch_bd<1>(P, sid, gal, nt, slots, st);
+        case 4: return qmr::launch_bd<4>(P, sid, gal, nt, slots, st);
+        case 9: return qmr::launch_bd<9>(P, sid, gal, nt, slots, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -110,7 +110,8 @@ struct scocg_plan {
     int32_t K = 0, nrhs = 0, seed0 = 0;
     int nt = 512, slots = 0, prec = 0;
     bool proj = false;        // projected (requested rows only) FP64 solve
-    bool qmr = false;         // shifted QMR over the real S-Lanczos basis
+    bool qmr = false;         // real S-Lanczos basis (QMR, or the COCG iterates if gal)
+    bool gal = false;
     int64_t nIp = 0;
     int64_t Mp = 0, slot_bytes = 0, out_count = 0;
     std::vector<int64_t> out_off;
@@ -756,14 +757,15 @@ extern "C" scocg_status scocg_plan_create(scocg_problem* P, const scocg_options*
     pl->nt = opt.threads ? opt.threads : 512;
     pl->Mp = std::max<int64_t>(64, (hm.maxM + 63) / 64 * 64);
     pl->proj = opt.projected && opt.precision == SCOCG_FP64 && !(spec && spec->out_mode == SCOCG_OUT_FULL_X);
-    pl->qmr = opt.method == SCOCG_METHOD_QMR;
-    if (opt.method != SCOCG_METHOD_COCG && opt.method != SCOCG_METHOD_QMR) {
+    pl->qmr = opt.method == SCOCG_METHOD_QMR || opt.method == SCOCG_METHOD_COCG_LANCZOS;
+    pl->gal = opt.method == SCOCG_METHOD_COCG_LANCZOS;
+    if (opt.method != SCOCG_METHOD_COCG && opt.method != SCOCG_METHOD_QMR && opt.method != SCOCG_METHOD_COCG_LANCZOS) {
         scocg_plan_free(pl);
         return fail(SCOCG_E_ARG, "unknown method %d", opt.method);
     }
     if (pl->qmr && (opt.precision != SCOCG_FP64 || (spec && spec->out_mode == SCOCG_OUT_FULL_X))) {
         scocg_plan_free(pl);
-        return fail(SCOCG_E_UNSUPPORTED, "the QMR method runs in FP64 with SELECTED_G output");
+        return fail(SCOCG_E_UNSUPPORTED, "the Lanczos-basis methods run in FP64 with SELECTED_G output");
     }
     if (pl->qmr) {
         int64_t maxout = 1;
@@ -843,7 +845,7 @@ extern "C" scocg_status scocg_plan_info(const scocg_plan* pl, int64_t* info) {
     info[4] = pl->seed0;
     info[5] = (int64_t)(pl->qmr ? scocg::qmr_lds_bytes(pl->K, pl->nt) : scocg::solver_lds_bytes(pl->K, pl->nt));
     info[6] = pl->prec;
-    info[7] = (pl->global ? 1 : 0) | (pl->proj ? 2 : 0) | (pl->qmr ? 4 : 0);
+    info[7] = (pl->global ? 1 : 0) | (pl->proj ? 2 : 0) | (pl->qmr ? 4 : 0) | (pl->gal ? 8 : 0);
     return SCOCG_OK;
 }
 
@@ -913,7 +915,7 @@ extern "C" scocg_status scocg_plan_run(scocg_plan* pl, void* stream, scocg_z* ou
     KParams k = make_kparams(pl, out, iters, status, resid);
     (void)hipGetLastError();   // drop any error another caller left on this thread
     HIP_TRY(scocg::launch_fill_i32(pl->dqueue, 0, 1, st));
-    if (pl->qmr) HIP_TRY(scocg::launch_qmr(k, P->bd, !P->has_S, pl->nt, pl->slots, st));
+    if (pl->qmr) HIP_TRY(scocg::launch_qmr(k, P->bd, !P->has_S, pl->gal, pl->nt, pl->slots, st));
     else HIP_TRY(scocg::launch_solver(k, P->bd, pl->proj ? 3 : pl->prec, !P->has_S, pl->nt, pl->slots, st));
     return SCOCG_OK;
 }

@@ -1,12 +1,15 @@
-"""GPU shifted QMR (method = QMR) against the QMR oracle on the same inputs,
-and its argument rules.  The parity rule is the projected COCG form's: per
-(RHS, shift) relative difference <= 1e-8 with equal status, iteration
-counts within 25%, else both inside the a-priori bound of the dense
-solution."""
+"""GPU solvers on the real S-Lanczos basis: shifted QMR (method = QMR)
+against the QMR oracle, and the COCG iterates on that basis (method =
+COCG_LANCZOS) against both the oracle of that form and the seed-switching
+COCG oracle (the same iterates in exact arithmetic); argument rules.
+
+The parity rule is the projected COCG form's: per (RHS, shift) relative
+difference <= 1e-8 with equal status, iteration counts within 25%, else
+both inside the a-priori bound of the dense solution."""
 import numpy as np
 import pytest
 
-from oracle import local_system, sqmr
+from oracle import local_system, scocg_lanczos, scocg_projected, sqmr
 from synth import bsr_to_scipy, make_config, make_problem
 from tests.parity import compare_rhs
 
@@ -19,13 +22,14 @@ def B(gpu_lib):
     return binding
 
 
-def _plan(B, prob, **opt):
+def _plan(B, prob, method=None, **opt):
     P = B.Problem(prob.H, prob.S)
     kw = dict(out_ptr=prob.out_ptr, out_rows=prob.out_rows)
     if prob.cluster_ptr is not None:
         kw.update(cluster_ptr=prob.cluster_ptr, cluster_atoms=prob.cluster_atoms)
     opt.setdefault("tol", prob.tol)
-    return P, B.Plan(P, prob.shifts, prob.rhs, method=B.METHOD_QMR, **kw, **opt)
+    method = B.METHOD_QMR if method is None else method
+    return P, B.Plan(P, prob.shifts, prob.rhs, method=method, **kw, **opt)
 
 
 CASES = {
@@ -61,6 +65,31 @@ def test_qmr_parity(B, case, threads):
         assert r["stats"][j][3] == 0          # no seed switches in the Lanczos form
     print(f"[qmr] {case} threads={threads}: worst rel err {worst:.2e}; shifts with other counts {len(report)}",
           flush=True)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("threads", [512, 1024])
+def test_cocg_on_lanczos_basis_parity(B, case, threads):
+    prob = CASES[case]()
+    P, plan = _plan(B, prob, method=B.METHOD_COCG_LANCZOS, threads=threads)
+    assert plan.info["global"] & 8
+    r = plan.solve()
+    Hcsr = bsr_to_scipy(prob.H)
+    Scsr = bsr_to_scipy(prob.S) if prob.S is not None else None
+    worst = [0.0, 0.0]
+    for j in range(prob.nrhs):
+        Hc, Sc, loc, orb = local_system(prob, j, Hcsr, Scsr)
+        b = np.zeros(orb.size)
+        b[loc] = 1.0
+        pos = np.searchsorted(orb, prob.outs(j))
+        for i, res in enumerate((scocg_lanczos(Hc, Sc, prob.shifts, b, prob.tol, rows=pos),
+                                 scocg_projected(Hc, Sc, prob.shifts, b.astype(np.complex128), pos, prob.tol))):
+            worst[i] = max(worst[i], compare_rhs(r["G"][j], r["iters"][j], r["status"][j], res, Hc, Sc, prob.shifts,
+                                                 b.astype(np.complex128), prob.tol, rows=pos, iter_frac=0.25,
+                                                 tag=f"rhs {j} oracle {i}"))
+        assert r["stats"][j][3] == 0
+    print(f"[cocg-lanczos] {case} threads={threads}: worst rel err vs its oracle {worst[0]:.2e}, "
+          f"vs the seed-switching oracle {worst[1]:.2e}", flush=True)
 
 
 def test_qmr_argument_rules(B):

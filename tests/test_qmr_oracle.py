@@ -107,3 +107,40 @@ def test_rows_subset_and_complex_rhs_rejected():
     assert np.array_equal(part.x, full.x[rows])
     with pytest.raises(ValueError):
         sqmr(H, S, prob.shifts, b * 1j, 1e-9)
+
+
+# ---- COCG iterates on the real Lanczos basis
+
+@pytest.mark.parametrize("with_S", [True, False])
+def test_lanczos_cocg_equals_seed_switching_form_at_fixed_steps(with_S):
+    """In exact arithmetic both forms produce the COCG (Galerkin) iterates;
+    before rounding differences grow (a few tens of steps) they agree to
+    rounding, iterate by iterate, with the residual norms too."""
+    from oracle import scocg, scocg_lanczos
+    prob = _prob(with_S, K=8)
+    H, S = bsr_to_scipy(prob.H), (bsr_to_scipy(prob.S) if prob.S is not None else None)
+    b = np.zeros(prob.M)
+    b[prob.rhs[0]] = 1.0
+    for m in (3, 8, 15):
+        a = scocg_lanczos(H, S, prob.shifts, b, 1e-300, maxiter=m)
+        c = scocg(H, S, prob.shifts, b.astype(np.complex128), 1e-300, maxiter=m)
+        assert np.abs(a.x - c.x).max() <= 1e-9 * np.abs(c.x).max()
+        assert np.allclose(a.resid, c.resid, rtol=1e-8)
+
+
+def test_lanczos_cocg_is_the_galerkin_solution_and_its_residual_is_exact():
+    from oracle import scocg_lanczos
+    prob = _prob(True, K=6)
+    m = 12
+    H, S, b, res, V, alpha, beta = _lanczos(prob, 0, m + 1)
+    Sd = S.toarray()
+    beta0 = np.sqrt(b @ np.linalg.solve(Sd, b))
+    T = np.diag(alpha[:m]) + np.diag(beta[:m - 1], 1) + np.diag(beta[:m - 1], -1)
+    a = scocg_lanczos(H, S, prob.shifts, b, 1e-300, maxiter=m)
+    Hd = H.toarray()
+    for k, zk in enumerate(prob.shifts):
+        y = np.linalg.solve(zk * np.eye(m) - T, beta0 * np.eye(m)[:, 0])
+        xg = V[:, :m] @ y
+        assert np.abs(a.x[:, k] - xg).max() <= 1e-10 * np.abs(xg).max()
+        true_res = np.linalg.norm(b - (zk * Sd - Hd) @ a.x[:, k])
+        assert abs(a.resid[k] - true_res) <= 1e-8 * true_res + 1e-13
