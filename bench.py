@@ -43,17 +43,18 @@ METHODS = {"cocg": 0, "qmr": 1, "cocg-lanczos": 2}
 _FORM_NAMES = {"qmr": "shifted QMR, real Lanczos basis", "lanczos": "COCG iterates on the real Lanczos basis"}
 
 
-def algorithmic_bytes_qmr(stats, nout, bd, has_S, w_share):
-    """Algorithmic bytes of one launch of the shifted QMR solver (real
-    Lanczos vectors, 8 bytes per element).  Per RHS and iteration:
-      shifts  80 K_a n + 8 n          (read d_{n-1}, d_{n-2}, x; write d_n, x on n = |I_j| rows; v on them)
+def algorithmic_bytes_qmr(stats, nout, bd, has_S, w_share, gal=False):
+    """Algorithmic bytes of one launch of the solvers on the real Lanczos
+    basis (8 bytes per vector element).  Per RHS and iteration:
+      shifts  80 K_a n + 8 n  QMR: read d_{n-1}, d_{n-2}, x; write d_n, x on n = |I_j| rows; v on them
+              64 K_a n + 8 n  COCG iterates: read p, x; write p, x
       Lanczos nb_H b^2 8 / w_share + 96 M_j   (H v; t = u - alpha w - beta w_prev; q^T t; the rescale)
       inner   k_in (nb_S b^2 8 / w_share + 48 M_j)"""
     outer, sum_upd, inner = stats[:, 0].astype(float), stats[:, 1].astype(float), stats[:, 2].astype(float)
     M, nblk = stats[:, 4].astype(float), stats[:, 5].astype(float)
     n = np.asarray(nout, dtype=float)
     blk = nblk * bd * bd * 8
-    shifts = sum_upd * n * 80 + outer * n * 8
+    shifts = sum_upd * n * (64 if gal else 80) + outer * n * 8
     lanczos = outer * (blk / w_share + 96 * M)
     a5 = inner * (blk / w_share + 48 * M) if has_S else 0.0
     return float(np.sum(shifts + lanczos + a5))
@@ -228,7 +229,7 @@ def measure_form(B, P, prob, kw, args, method, stream):
     nout = np.diff(prob.out_ptr)
     w_share = min(plan.info["slots"], prob.nrhs) if prob.cluster_ptr is None else 1
     if qmr:
-        alg = algorithmic_bytes_qmr(stats, nout, prob.bdim, prob.S is not None, w_share)
+        alg = algorithmic_bytes_qmr(stats, nout, prob.bdim, prob.S is not None, w_share, gal)
     else:
         alg = algorithmic_bytes(stats, nout, prob.nshift, prob.bdim, prob.S is not None, PREC[args.precision],
                                 projected, w_share, True)
