@@ -2,7 +2,9 @@
 
 One step is one full solve of the workload (every RHS, every shift, to
 relative residual 1e-6) by the persistent HIP solver, with H, S, the cluster
-maps and all working memory already resident in HBM.  A pair counts as
+maps and all working memory already resident in HBM.  The default form
+computes the shifted COCG iterates on the real S-Lanczos basis; the
+seed-switching COCG form is timed in the same run and reported beside it.  A pair counts as
 converged only if its FP64 residual ||b - (z_k S - H) x|| / ||b|| is
 <= 1e-6: the true residual audited on the device after the solve in the
 full-x form, the FP64 recursive estimate in the projected form.
