@@ -34,11 +34,13 @@ def _plan(B, prob, **kw):
     return P, B.Plan(P, prob.shifts, prob.rhs, **extra)
 
 
-@pytest.mark.parametrize("projected", [1, 0])
-def test_graph_replay_matches_eager(B, projected):
+@pytest.mark.parametrize("form", ["projected", "full", "lanczos", "qmr"])
+def test_graph_replay_matches_eager(B, form):
     import torch
     prob = _cluster()
-    P, plan = _plan(B, prob, projected=projected)
+    opt = {"projected": dict(projected=1), "full": dict(projected=0),
+           "lanczos": dict(method=B.METHOD_COCG_LANCZOS), "qmr": dict(method=B.METHOD_QMR)}[form]
+    P, plan = _plan(B, prob, **opt)
     eager = plan.solve()
     s = torch.cuda.Stream()
     bufs = plan.alloc_outputs()
@@ -63,13 +65,14 @@ def test_graph_replay_matches_eager(B, projected):
         del y
 
 
-def test_queue_order_changes_nothing(B):
+@pytest.mark.parametrize("method", [0, 2])
+def test_queue_order_changes_nothing(B, method):
     prob = _cluster(nrhs=16)
-    P, plan = _plan(B, prob)
+    P, plan = _plan(B, prob, method=method)
     ref = plan.solve()
     rng = np.random.default_rng(3)
     for order in (np.arange(prob.nrhs)[::-1], rng.permutation(prob.nrhs)):
-        P2, plan2 = _plan(B, prob, order=order.astype(np.int32))
+        P2, plan2 = _plan(B, prob, method=method, order=order.astype(np.int32))
         r = plan2.solve()
         for j in range(prob.nrhs):
             assert np.array_equal(r["G"][j], ref["G"][j])
