@@ -243,7 +243,7 @@ def measure_form(B, P, prob, kw, args, method, stream):
         "inner_per_outer": float(stats[:, 2].sum() / max(1, stats[:, 0].sum())),
         "fallback_iterations": int(stats[:, 7].sum()),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args, form_key),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args, form_key, alg),
                      "kernel": "k_sqmr (persistent solver)" if qmr else "k_scocg (persistent solver)",
                      "kernel_ms": kernel_s * 1e3, "algorithmic_bytes": alg},
     }
@@ -405,11 +405,12 @@ def _kernel_source_hash(form="proj"):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(args, form):
+def measured_traffic(args, form, alg_bytes):
     """HBM bytes per launch from the committed rocprofv3 counter summary of
     this workload and form (FETCH_SIZE + WRITE_SIZE, scaled by a plain
-    copy's reading), or None if there is none or the kernel sources changed
-    since."""
+    copy's reading), or None if there is none, the kernel sources changed
+    since, or this run is not the profiled one (its algorithmic bytes differ:
+    another RHS count, iteration cap or tolerance)."""
     key = f"{args.workload}_{args.precision}_{form}"
     path = os.path.join(ROOT, "profiles", f"k_scocg_{key}_traffic.json")
     if not os.path.exists(path):
@@ -417,6 +418,9 @@ def measured_traffic(args, form):
     with open(path) as f:
         t = json.load(f)
     if t.get("kernel_source_hash") != _kernel_source_hash(form):
+        return None
+    ref = t.get("algorithmic_bytes_per_launch")
+    if not ref or abs(alg_bytes - ref) > 1e-3 * ref:
         return None
     return t.get("hbm_bytes_per_launch")
 

@@ -327,6 +327,46 @@ scocg_status scocg_mlp_train_step(float* w, float* adam_m, float* adam_v, const 
                                   const int32_t* idx, int64_t m, float lr, int32_t step, float* loss,
                                   float* grad, float* work, void* stream);
 
+/*
+ * A whole training run of the cost network on host buffers (the learned
+ * binning of the RHS queue; the network and its Adam steps run on the
+ * current device through the two calls above).  feats: host float[n][16]
+ * (raw features, as scocg_features writes them); log_iters: host float[n]
+ * (targets, log outer iterations).  Every feature is z-scored with its
+ * mean and standard deviation over the n samples (sd 1 where constant); a
+ * fraction val_frac of the samples, drawn from the seeded stream, is held
+ * out, the rest visited in a freshly shuffled order each epoch in batches
+ * of `batch`; the weights of the epoch with the lowest validation loss are
+ * returned (the last epoch's when val_frac = 0).  model_out: host float
+ * [scocg_mlp_model_floats()] = the 5313 weights, then the 16 feature means,
+ * then the 16 standard deviations; val_loss (may be NULL): the best
+ * validation MSE (NaN when val_frac = 0).  Synchronous; allocates and frees
+ * its own device buffers.  Deterministic for a given seed.  Errors: E_ARG
+ * (NULL pointer, n < 2, non-finite target, epochs or batch < 1, lr <= 0,
+ * val_frac outside [0, 1)), E_NOMEM, E_DEVICE.
+ */
+typedef struct {
+    int32_t epochs;             /* default 200 */
+    int32_t batch;              /* default 256 */
+    float lr;                   /* Adam step size, default 1e-3 */
+    float val_frac;             /* held-out fraction, default 0.2 */
+    uint64_t seed;              /* initial weights and sample order (splitmix64 stream) */
+    const float* init_weights;  /* host float[5313], or NULL: Kaiming-uniform weights (bound
+                                   sqrt(6 / fan_in)) and zero biases drawn from seed */
+} scocg_mlp_cfg;
+void scocg_mlp_cfg_default(scocg_mlp_cfg* cfg);
+/* Floats of a trained model: 5313 weights + 16 means + 16 standard deviations. */
+int64_t scocg_mlp_model_floats(void);
+scocg_status scocg_mlp_train(const float* feats, const float* log_iters, int64_t n, const scocg_mlp_cfg* cfg,
+                             float* model_out, double* val_loss);
+/*
+ * pred[s] = network(z-scored feats[s]) for s < n with a model from
+ * scocg_mlp_train; host buffers (model float[scocg_mlp_model_floats()],
+ * feats float[n][16], pred float[n]); synchronous.  Errors: E_ARG (NULL
+ * pointer, n < 0, a standard deviation <= 0 in the model), E_NOMEM, E_DEVICE.
+ */
+scocg_status scocg_mlp_predict(const float* model, const float* feats, int64_t n, float* pred);
+
 /* Energy integration of G (the density of states and the density matrix,
  * Sec. 2-3: the Green's function as the analysis object).  G is the output
  * buffer a previous scocg_plan_run of this plan wrote ([rhs][shift][row],
@@ -364,6 +404,32 @@ scocg_status scocg_solve(scocg_problem* P, const scocg_options* opt, int32_t nsh
                          const scocg_z* shifts, int32_t nrhs, const int32_t* rhs_index,
                          const scocg_rhs_spec* spec, scocg_z* out, int32_t* iters,
                          int8_t* status, double* resid);
+
+/*
+ * The same solve on caller-owned DEVICE output buffers, asynchronous on
+ * `stream` (a hipStream_t; NULL = the default stream): validates the inputs
+ * and builds the plan exactly as scocg_plan_create (shifts, rhs_index and the
+ * spec arrays are HOST arrays, because the per-RHS cluster maps are built on
+ * the host), then enqueues the run as scocg_plan_run does and returns.  out:
+ * device scocg_z[K * sum_j nout_j] in the [rhs][shift][row] layout of
+ * scocg_plan_run (nout_j = out_ptr[j+1] - out_ptr[j] for SELECTED_G; M, or
+ * bdim times the cluster's atom count, for FULL_X); iters, status, resid:
+ * device [nrhs][K] or NULL.  The problem keeps the plan until scocg_sync.
+ * Errors: those of scocg_plan_create and scocg_plan_run, returned before
+ * anything is enqueued.
+ */
+scocg_status scocg_solve_device(scocg_problem* P, const scocg_options* opt, int32_t nshift,
+                                const scocg_z* shifts, int32_t nrhs, const int32_t* rhs_index,
+                                const scocg_rhs_spec* spec, scocg_z* out, int32_t* iters, int8_t* status,
+                                double* resid, void* stream);
+/*
+ * Waits for every scocg_solve_device of P still pending (on its stream) and
+ * frees their plans.  Returns OK, W_PARTIAL if some pair of those solves
+ * did not converge (read from their status buffers; a solve given status =
+ * NULL is not checked), or E_DEVICE.  scocg_problem_free calls it.  One
+ * problem per host thread: solves and syncs of one problem must not overlap.
+ */
+scocg_status scocg_sync(scocg_problem* P);
 
 #ifdef __cplusplus
 }

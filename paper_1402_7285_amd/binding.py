@@ -33,7 +33,8 @@ EXPORTS = (
     "scocg_plan_run", "scocg_plan_stats", "scocg_solve", "scocg_plan_capture", "scocg_plan_replay",
     "scocg_autotune", "scocg_features", "scocg_mlp_nparams", "scocg_mlp_work_floats", "scocg_mlp_forward",
     "scocg_mlp_train_step", "scocg_plan_integrate", "scocg_matrix_from_mtx", "scocg_matrix_shape",
-    "scocg_matrix_export_bsr",
+    "scocg_matrix_export_bsr", "scocg_solve_device", "scocg_sync", "scocg_mlp_cfg_default",
+    "scocg_mlp_model_floats", "scocg_mlp_train", "scocg_mlp_predict",
 )
 
 
@@ -61,6 +62,11 @@ class scocg_rhs_spec(C.Structure):
 
 _VP = C.c_void_p
 _LIB = None
+
+
+class scocg_mlp_cfg(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("val_frac", C.c_float),
+                ("seed", C.c_uint64), ("init_weights", C.c_void_p)]
 
 
 def _declare(lib):
@@ -97,6 +103,13 @@ def _declare(lib):
                                 i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_double)]),
         "scocg_solve": (st, [_VP, C.POINTER(scocg_options), i32, _VP, i32, _VP,
                              C.POINTER(scocg_rhs_spec), _VP, _VP, _VP, _VP]),
+        "scocg_solve_device": (st, [_VP, C.POINTER(scocg_options), i32, _VP, i32, _VP,
+                                    C.POINTER(scocg_rhs_spec), _VP, _VP, _VP, _VP, _VP]),
+        "scocg_sync": (st, [_VP]),
+        "scocg_mlp_cfg_default": (None, [C.POINTER(scocg_mlp_cfg)]),
+        "scocg_mlp_model_floats": (i64, []),
+        "scocg_mlp_train": (st, [_VP, _VP, i64, C.POINTER(scocg_mlp_cfg), _VP, C.POINTER(C.c_double)]),
+        "scocg_mlp_predict": (st, [_VP, _VP, i64, _VP]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -306,6 +319,61 @@ def scocg_solve(problem, opt, shifts, rhs_index, spec: _Spec, nout_total):
     code = _check(load().scocg_solve(problem, C.byref(opt), int(K), zp, int(R), _ptr(rhs), C.byref(spec.struct),
                                      _ptr(out), _ptr(iters), _ptr(status), _ptr(resid)))
     return out[:nout_total], iters.reshape(R, K), status.reshape(R, K), resid.reshape(R, K), code
+
+
+def scocg_solve_device(problem, opt, shifts, rhs_index, spec: _Spec, out, iters=None, status=None, resid=None,
+                       stream=None):
+    """Enqueue a solve into caller-owned torch CUDA tensors on ``stream``
+    (a torch.cuda.Stream or None); finish it with ``scocg_sync(problem)``."""
+    z, zp = _shifts(shifts)
+    rhs = np.ascontiguousarray(rhs_index, dtype=np.int32)
+    return _check(load().scocg_solve_device(problem, C.byref(opt), int(z.size), zp, int(rhs.size), _ptr(rhs),
+                                            C.byref(spec.struct), _tptr(out), _tptr(iters), _tptr(status),
+                                            _tptr(resid), _sp(stream)))
+
+
+def scocg_sync(problem):
+    """Wait for the problem's pending device-buffer solves; returns OK or W_PARTIAL."""
+    return _check(load().scocg_sync(problem))
+
+
+def scocg_mlp_cfg_default(**overrides) -> scocg_mlp_cfg:
+    cfg = scocg_mlp_cfg()
+    load().scocg_mlp_cfg_default(C.byref(cfg))
+    for k, v in overrides.items():
+        setattr(cfg, k, v)
+    return cfg
+
+
+def scocg_mlp_model_floats() -> int:
+    return int(load().scocg_mlp_model_floats())
+
+
+def scocg_mlp_train(feats, log_iters, init_weights=None, **cfg_overrides):
+    """Whole training run on host arrays; returns (model float32
+    [scocg_mlp_model_floats()], best validation loss)."""
+    F = np.ascontiguousarray(feats, dtype=np.float32)
+    t = np.ascontiguousarray(log_iters, dtype=np.float32)
+    if F.ndim != 2 or F.shape[1] != 16 or t.shape != (F.shape[0],):
+        raise ValueError("feats must be [n, 16] and log_iters [n]")
+    w0 = None if init_weights is None else np.ascontiguousarray(init_weights, dtype=np.float32)
+    cfg = scocg_mlp_cfg_default(**cfg_overrides)
+    cfg.init_weights = None if w0 is None else w0.ctypes.data
+    model = np.zeros(scocg_mlp_model_floats(), dtype=np.float32)
+    vl = C.c_double(0.0)
+    _check(load().scocg_mlp_train(_ptr(F), _ptr(t), int(F.shape[0]), C.byref(cfg), _ptr(model), C.byref(vl)))
+    return model, float(vl.value)
+
+
+def scocg_mlp_predict(model, feats):
+    """Predictions of a scocg_mlp_train model for host features [n, 16]."""
+    m = np.ascontiguousarray(model, dtype=np.float32)
+    F = np.ascontiguousarray(feats, dtype=np.float32)
+    if m.size != scocg_mlp_model_floats() or F.ndim != 2 or F.shape[1] != 16:
+        raise ValueError("model size or feature shape")
+    y = np.zeros(F.shape[0], dtype=np.float32)
+    _check(load().scocg_mlp_predict(_ptr(m), _ptr(F), int(F.shape[0]), _ptr(y)))
+    return y
 
 
 # ---------------------------------------------------------------------------

@@ -102,6 +102,15 @@ struct scocg_problem {
     int64_t* dRowptr = nullptr;    // merged pattern on device (global systems)
     int32_t* dCol = nullptr;
     int32_t* dIota = nullptr;
+    // device-buffer solves enqueued by scocg_solve_device and not yet
+    // synchronised: their plans stay alive until scocg_sync
+    struct Pending {
+        scocg_plan* pl;
+        hipStream_t st;
+        const int8_t* status;
+        int64_t n;
+    };
+    std::vector<Pending> pending;
 };
 
 struct scocg_plan {
@@ -338,6 +347,7 @@ extern "C" void scocg_matrix_free(scocg_matrix* m) { delete m; }
 extern "C" void scocg_problem_free(scocg_problem* p) {
     if (!p) return;
     (void)hipSetDevice(p->device);
+    (void)scocg_sync(p);          // finishes and frees any device-buffer solve still pending
     dev_free(p->dH);
     dev_free(p->dS);
     dev_free(p->dH32);
@@ -997,6 +1007,64 @@ extern "C" scocg_status scocg_solve(scocg_problem* P, const scocg_options* opt, 
 }
 
 // ---------------------------------------------------------------------------
+// device-buffer solve: plan_create + plan_run, the plan kept until scocg_sync
+// ---------------------------------------------------------------------------
+extern "C" scocg_status scocg_solve_device(scocg_problem* P, const scocg_options* opt, int32_t nshift,
+                                           const scocg_z* shifts, int32_t nrhs, const int32_t* rhs_index,
+                                           const scocg_rhs_spec* spec, scocg_z* out, int32_t* iters, int8_t* status,
+                                           double* resid, void* stream) {
+    if (!P) return fail(SCOCG_E_ARG, "problem is NULL");
+    scocg_plan* pl = nullptr;
+    scocg_status st = scocg_plan_create(P, opt, nshift, shifts, nrhs, rhs_index, spec, &pl);
+    if (st < 0) return st;
+    if (nrhs == 0) {
+        scocg_plan_free(pl);
+        return SCOCG_OK;
+    }
+    st = scocg_plan_run(pl, stream, out, iters, status, resid);
+    if (st < 0) {
+        const std::string msg = scocg_last_error();
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        scocg_plan_free(pl);
+        return fail(st, "%s", msg.c_str());
+    }
+    try {
+        P->pending.push_back(scocg_problem::Pending{pl, (hipStream_t)stream, status, (int64_t)nrhs * nshift});
+    } catch (...) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        scocg_plan_free(pl);
+        return fail(SCOCG_E_NOMEM, "host allocation");
+    }
+    return SCOCG_OK;
+}
+
+extern "C" scocg_status scocg_sync(scocg_problem* P) {
+    if (!P) return fail(SCOCG_E_ARG, "problem is NULL");
+    if (P->pending.empty()) return SCOCG_OK;
+    scocg_status res = SCOCG_OK;
+    bool partial = false;
+    std::string err;
+    if (hipSetDevice(P->device) != hipSuccess) err = "hipSetDevice failed";
+    std::vector<int8_t> h;
+    for (const auto& q : P->pending) {
+        hipError_t e = q.st ? hipStreamSynchronize(q.st) : hipDeviceSynchronize();
+        if (e == hipSuccess && q.status && q.n > 0) {
+            h.resize((size_t)q.n);
+            e = hipMemcpy(h.data(), q.status, (size_t)q.n, hipMemcpyDeviceToHost);
+            if (e == hipSuccess)
+                for (int8_t v : h)
+                    if (v != SCOCG_CONVERGED) { partial = true; break; }
+        }
+        if (e != hipSuccess && err.empty()) err = hipGetErrorString(e);
+        scocg_plan_free(q.pl);
+    }
+    P->pending.clear();
+    if (!err.empty()) return fail(SCOCG_E_DEVICE, "scocg_sync: %s", err.c_str());
+    if (partial) res = SCOCG_W_PARTIAL;
+    return res;
+}
+
+// ---------------------------------------------------------------------------
 // graph capture / replay
 // ---------------------------------------------------------------------------
 extern "C" scocg_status scocg_plan_capture(scocg_plan* pl, void* stream, scocg_z* out, int32_t* iters,
@@ -1139,5 +1207,174 @@ extern "C" scocg_status scocg_mlp_train_step(float* w, float* adam_m, float* ada
     (void)hipGetLastError();
     HIP_TRY(scocg::launch_mlp_grad(w, x, t, idx, m, partial, loss_part, scocg::GRAD_BLOCKS, st));
     HIP_TRY(scocg::launch_mlp_adam(w, adam_m, adam_v, partial, loss_part, nparts, m, lr, step, grad, loss, st));
+    return SCOCG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// whole training run and prediction on host buffers
+// ---------------------------------------------------------------------------
+namespace {
+
+// splitmix64: the initial weights and the batch order of scocg_mlp_train
+struct Mix64 {
+    uint64_t s;
+    uint64_t next() {
+        uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    double uniform() { return (double)(next() >> 11) * (1.0 / 9007199254740992.0); }
+    int64_t below(int64_t n) { return (int64_t)(uniform() * (double)n); }
+};
+
+void shuffle(std::vector<int32_t>& v, Mix64& r) {
+    for (int64_t i = (int64_t)v.size() - 1; i > 0; --i) std::swap(v[i], v[r.below(i + 1)]);
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+    bool alloc(size_t b) { return hipMalloc(&p, std::max<size_t>(b, 16)) == hipSuccess; }
+    template <class T> T* as() const { return (T*)p; }
+};
+
+}  // namespace
+
+extern "C" int64_t scocg_mlp_model_floats(void) { return scocg::NPARAM + 2 * scocg::NIN; }
+
+extern "C" void scocg_mlp_cfg_default(scocg_mlp_cfg* cfg) {
+    if (!cfg) return;
+    cfg->epochs = 200;
+    cfg->batch = 256;
+    cfg->lr = 1e-3f;
+    cfg->val_frac = 0.2f;
+    cfg->seed = 0x14027285ull;
+    cfg->init_weights = nullptr;
+}
+
+extern "C" scocg_status scocg_mlp_train(const float* feats, const float* log_iters, int64_t n,
+                                        const scocg_mlp_cfg* cfg_in, float* model_out, double* val_loss) {
+    using namespace scocg;
+    if (!feats || !log_iters || !model_out || n < 2) return fail(SCOCG_E_ARG, "bad argument (n >= 2 needed)");
+    scocg_mlp_cfg cfg;
+    scocg_mlp_cfg_default(&cfg);
+    if (cfg_in) cfg = *cfg_in;
+    if (cfg.epochs < 1 || cfg.batch < 1 || !(cfg.lr > 0.f) || !(cfg.val_frac >= 0.f && cfg.val_frac < 1.f))
+        return fail(SCOCG_E_ARG, "epochs, batch >= 1, lr > 0, 0 <= val_frac < 1");
+    // z-score every feature (constant features keep sd = 1)
+    std::vector<double> mu(NIN, 0.0), sd(NIN, 0.0);
+    for (int64_t r = 0; r < n; ++r)
+        for (int f = 0; f < NIN; ++f) mu[f] += feats[r * NIN + f];
+    for (int f = 0; f < NIN; ++f) mu[f] /= (double)n;
+    for (int64_t r = 0; r < n; ++r)
+        for (int f = 0; f < NIN; ++f) {
+            const double d = feats[r * NIN + f] - mu[f];
+            sd[f] += d * d;
+        }
+    for (int f = 0; f < NIN; ++f) {
+        sd[f] = std::sqrt(sd[f] / (double)n);
+        if (!(sd[f] > 0.0)) sd[f] = 1.0;
+    }
+    std::vector<float> X((size_t)n * NIN), T((size_t)n);
+    for (int64_t r = 0; r < n; ++r) {
+        for (int f = 0; f < NIN; ++f) X[r * NIN + f] = (float)((feats[r * NIN + f] - mu[f]) / sd[f]);
+        T[r] = log_iters[r];
+        if (!std::isfinite(T[r])) return fail(SCOCG_E_ARG, "log_iters[%lld] is not finite", (long long)r);
+    }
+    Mix64 rng{cfg.seed};
+    std::vector<float> w(NPARAM, 0.f);
+    if (cfg.init_weights) {
+        std::memcpy(w.data(), cfg.init_weights, sizeof(float) * NPARAM);
+    } else {
+        // Kaiming-uniform weights (bound sqrt(6 / fan_in)), zero biases
+        auto fill = [&](int off, int cnt, int fan_in) {
+            const double b = std::sqrt(6.0 / fan_in);
+            for (int i = 0; i < cnt; ++i) w[off + i] = (float)((2.0 * rng.uniform() - 1.0) * b);
+        };
+        fill(OFF_W1, NH * NIN, NIN);
+        fill(OFF_W2, NH * NH, NH);
+        fill(OFF_W3, NH, NH);
+    }
+    std::vector<int32_t> perm((size_t)n);
+    for (int64_t r = 0; r < n; ++r) perm[r] = (int32_t)r;
+    shuffle(perm, rng);
+    const int64_t nval = (int64_t)std::llround((double)cfg.val_frac * (double)n);
+    if (n - nval < 1) return fail(SCOCG_E_ARG, "no training samples left after the validation split");
+    std::vector<int32_t> val(perm.begin(), perm.begin() + nval), tr(perm.begin() + nval, perm.end());
+
+    DevBuf dX, dT, dw, dm, dv, didx, dloss, dwork;
+    const int64_t nwork = scocg_mlp_work_floats();
+    if (!dX.alloc(sizeof(float) * X.size()) || !dT.alloc(sizeof(float) * T.size()) ||
+        !dw.alloc(sizeof(float) * NPARAM) || !dm.alloc(sizeof(float) * NPARAM) || !dv.alloc(sizeof(float) * NPARAM) ||
+        !didx.alloc(sizeof(int32_t) * (size_t)n) || !dloss.alloc(sizeof(float)) ||
+        !dwork.alloc(sizeof(float) * (size_t)nwork))
+        return fail(SCOCG_E_NOMEM, "training buffers");
+    HIP_TRY(hipMemcpy(dX.p, X.data(), sizeof(float) * X.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dT.p, T.data(), sizeof(float) * T.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dw.p, w.data(), sizeof(float) * NPARAM, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(dm.p, 0, sizeof(float) * NPARAM));
+    HIP_TRY(hipMemset(dv.p, 0, sizeof(float) * NPARAM));
+    std::vector<float> best = w;
+    double best_loss = INFINITY;
+    int32_t step = 0;
+    const int64_t ntr = (int64_t)tr.size();
+    for (int ep = 0; ep < cfg.epochs; ++ep) {
+        shuffle(tr, rng);
+        // the epoch's batch order goes up once; each step reads its slice
+        HIP_TRY(hipMemcpy(didx.p, tr.data(), sizeof(int32_t) * (size_t)ntr, hipMemcpyHostToDevice));
+        for (int64_t b0 = 0; b0 < ntr; b0 += cfg.batch) {
+            const int64_t m = std::min<int64_t>(cfg.batch, ntr - b0);
+            scocg_status st = scocg_mlp_train_step(dw.as<float>(), dm.as<float>(), dv.as<float>(), dX.as<float>(),
+                                                   dT.as<float>(), didx.as<int32_t>() + b0, m, cfg.lr, ++step,
+                                                   nullptr, nullptr, dwork.as<float>(), nullptr);
+            if (st < 0) return st;
+        }
+        if (nval > 0) {
+            HIP_TRY(hipMemcpy(didx.p, val.data(), sizeof(int32_t) * (size_t)nval, hipMemcpyHostToDevice));
+            scocg_status st = scocg_mlp_train_step(dw.as<float>(), nullptr, nullptr, dX.as<float>(), dT.as<float>(),
+                                                   didx.as<int32_t>(), nval, 0.f, 1, dloss.as<float>(), nullptr,
+                                                   dwork.as<float>(), nullptr);
+            if (st < 0) return st;
+            float vl = 0.f;
+            HIP_TRY(hipMemcpy(&vl, dloss.p, sizeof(float), hipMemcpyDeviceToHost));
+            if (vl < best_loss) {
+                best_loss = vl;
+                HIP_TRY(hipMemcpy(best.data(), dw.p, sizeof(float) * NPARAM, hipMemcpyDeviceToHost));
+            }
+        }
+    }
+    if (nval == 0) HIP_TRY(hipMemcpy(best.data(), dw.p, sizeof(float) * NPARAM, hipMemcpyDeviceToHost));
+    HIP_TRY(hipDeviceSynchronize());
+    std::memcpy(model_out, best.data(), sizeof(float) * NPARAM);
+    for (int f = 0; f < NIN; ++f) {
+        model_out[NPARAM + f] = (float)mu[f];
+        model_out[NPARAM + NIN + f] = (float)sd[f];
+    }
+    if (val_loss) *val_loss = nval > 0 ? best_loss : NAN;
+    return SCOCG_OK;
+}
+
+extern "C" scocg_status scocg_mlp_predict(const float* model, const float* feats, int64_t n, float* pred) {
+    using namespace scocg;
+    if (n < 0) return fail(SCOCG_E_ARG, "n < 0");
+    if (n == 0) return SCOCG_OK;
+    if (!model || !feats || !pred) return fail(SCOCG_E_ARG, "NULL argument");
+    const float* mu = model + NPARAM;
+    const float* sd = model + NPARAM + NIN;
+    for (int f = 0; f < NIN; ++f)
+        if (!(sd[f] > 0.f)) return fail(SCOCG_E_ARG, "model: feature %d has sd <= 0", f);
+    std::vector<float> X((size_t)n * NIN);
+    for (int64_t r = 0; r < n; ++r)
+        for (int f = 0; f < NIN; ++f) X[r * NIN + f] = (feats[r * NIN + f] - mu[f]) / sd[f];
+    DevBuf dX, dw, dy;
+    if (!dX.alloc(sizeof(float) * X.size()) || !dw.alloc(sizeof(float) * NPARAM) || !dy.alloc(sizeof(float) * n))
+        return fail(SCOCG_E_NOMEM, "prediction buffers");
+    HIP_TRY(hipMemcpy(dX.p, X.data(), sizeof(float) * X.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dw.p, model, sizeof(float) * NPARAM, hipMemcpyHostToDevice));
+    scocg_status st = scocg_mlp_forward(dw.as<float>(), dX.as<float>(), n, dy.as<float>(), nullptr);
+    if (st < 0) return st;
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(pred, dy.p, sizeof(float) * n, hipMemcpyDeviceToHost));
     return SCOCG_OK;
 }

@@ -97,3 +97,29 @@ def test_matrix_from_csr_matches_bsr():
     with pytest.raises(B.ScocgError) as e:
         B.scocg_matrix_from_csr(A.shape[0], Au.indptr.astype(np.int64), Au.indices, Au.data, 4)
     assert e.value.code == B.E_NOT_SYMMETRIC
+
+
+def test_new_entry_points_reject_bad_arguments_on_the_host():
+    # argument checks that run before any device call
+    with pytest.raises(B.ScocgError) as ei:
+        B.scocg_sync(None)
+    assert ei.value.code == B.E_ARG
+    with pytest.raises(B.ScocgError) as ei:
+        B.scocg_mlp_train(np.zeros((1, 16)), np.zeros(1))
+    assert ei.value.code == B.E_ARG
+    with pytest.raises(B.ScocgError) as ei:
+        B.scocg_mlp_train(np.zeros((4, 16)), np.array([0.0, 1.0, np.nan, 2.0]))
+    assert ei.value.code == B.E_ARG
+    with pytest.raises(B.ScocgError) as ei:
+        B.scocg_mlp_train(np.zeros((4, 16)), np.zeros(4), epochs=0)
+    assert ei.value.code == B.E_ARG
+    with pytest.raises(B.ScocgError) as ei:
+        B.scocg_mlp_train(np.zeros((4, 16)), np.zeros(4), val_frac=1.0)
+    assert ei.value.code == B.E_ARG
+    model = np.zeros(B.scocg_mlp_model_floats(), dtype=np.float32)      # sd = 0: not a trained model
+    with pytest.raises(B.ScocgError) as ei:
+        B.scocg_mlp_predict(model, np.zeros((3, 16)))
+    assert ei.value.code == B.E_ARG
+    assert B.scocg_mlp_model_floats() == B.scocg_mlp_nparams() + 32
+    cfg = B.scocg_mlp_cfg_default()
+    assert (cfg.epochs, cfg.batch, cfg.val_frac) == (200, 256, pytest.approx(0.2)) and cfg.init_weights is None

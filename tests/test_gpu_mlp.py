@@ -136,3 +136,30 @@ def test_learned_order_on_solver_logs(B):
             assert np.array_equal(out[a:b_].reshape(test_p.nshift, -1), ref["G"][j])
     print("[mlp] solve time by queue order (24 workgroups): "
           + ", ".join(f"{k} {v * 1e3:.1f} ms" for k, v in times.items()), flush=True)
+
+
+def test_whole_training_run_and_prediction(B):
+    """scocg_mlp_train / scocg_mlp_predict on host buffers: deterministic
+    for a seed, learns the target, stores the feature standardisation, and
+    predicts what the FP64 oracle network gives on the standardised input."""
+    X, t, w = _mlp_data(n=600, seed=5)
+    F = X * 3.0 + 1.0                                         # raw features: the model z-scores them
+    kw = dict(epochs=120, batch=64, lr=3e-3, seed=11)
+    model, vl = B.scocg_mlp_train(F, t, **kw)
+    model2, vl2 = B.scocg_mlp_train(F, t, **kw)
+    assert np.array_equal(model, model2) and vl == vl2
+    NP = B.scocg_mlp_nparams()
+    mu, sd = model[NP:NP + 16], model[NP + 16:]
+    np.testing.assert_allclose(mu, F.astype(np.float64).mean(0), rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(sd, F.astype(np.float64).std(0), rtol=1e-5)
+    y = B.scocg_mlp_predict(model, F)
+    Z = (F.astype(np.float64) - mu) / sd
+    yo, _ = OM.forward(model[:NP].astype(np.float64), Z)
+    assert np.abs(y - yo).max() <= 1e-4 * max(1.0, np.abs(yo).max())
+    corr = np.corrcoef(y, t)[0, 1]
+    print(f"[mlp-train] validation MSE {vl:.4f} (target variance {np.var(t):.4f}), correlation {corr:.3f}",
+          flush=True)
+    assert vl < 0.5 * np.var(t) and corr > 0.8
+    # given initial weights and a negligible step, the weights stay where they started
+    m0, _ = B.scocg_mlp_train(F, t, init_weights=w, epochs=1, lr=1e-12, val_frac=0.0)
+    assert np.abs(m0[:NP] - w).max() < 1e-6
