@@ -376,12 +376,29 @@ scocg_status scocg_mlp_predict(const float* model, const float* feats, int64_t n
  * if ldos is not NULL, ldos[j*nshift + k] = -(1/pi) Im G_jj(z_k) (NaN when
  * orbital j is not among RHS j's output rows).  weights: the caller's
  * quadrature weights on the real parts of the shifts (e.g. trapezoid for an
- * equally spaced mesh).  G, weights, rho (out_count doubles) and ldos
- * (nrhs*nshift doubles) are device pointers owned by the caller; the call is
+ * equally spaced mesh).  G, weights, rho (one double per output row: the
+ * last of scocg_plan_out_offsets, i.e. scocg_plan_out_count / nshift) and
+ * ldos (nrhs*nshift doubles) are device pointers owned by the caller; the call is
  * asynchronous on `stream`.  Errors: E_ARG (NULL pointer, non-finite mu,
  * negative or non-finite kT), E_DEVICE. */
 scocg_status scocg_plan_integrate(scocg_plan* plan, void* stream, const scocg_z* G, const double* weights,
                                   double mu, double kT, double* rho, double* ldos);
+
+/*
+ * Integrated crystal-orbital Hamilton population (COHP) of every output
+ * pair, the bond analysis the paper builds on G (Sec. 2: a COHP extension
+ * based on the Green's function):
+ *   cohp[o] = H_{row(o), j} rho[o]
+ * for output row o of RHS j, with rho as scocg_plan_integrate of this plan
+ * wrote it (device double[rows], rows = sum_j nout_j); cohp has the same
+ * layout.  H_{row(o), j} is gathered once per output row when the plan is
+ * built (0 where the atoms of row(o) and j share no block).  Summed over the
+ * orbitals of an atom b, cohp is the population of the bond between orbital
+ * j and atom b; summed over every row of a FULL_X output it is (H rho)_jj,
+ * orbital j's part of the band energy tr(rho H).  Asynchronous on `stream`.
+ * Errors: E_ARG (NULL pointer), E_DEVICE.
+ */
+scocg_status scocg_plan_cohp(scocg_plan* plan, void* stream, const double* rho, double* cohp);
 
 /*
  * Per-RHS counters of the last run, copied to host int64[nrhs * SCOCG_NSTAT]

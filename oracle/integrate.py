@@ -14,6 +14,12 @@ In the S-orthonormal eigenbasis (H y_n = eps_n S y_n), G_ij(z) =
 sum_n y_in y_jn / (z - eps_n), so -(1/pi) Im G is a sum of Lorentzians of
 half-width eta and rho_ij tends to sum_n f(eps_n) y_in y_jn as eta -> 0 on
 a fine mesh.  The sums below are written out in that order; no blocking.
+
+The paper's bond analysis (Sec. 2, a COHP extension based on G) splits the
+band energy tr(rho H) = sum_ij H_ji rho_ij into pair terms: the integrated
+crystal-orbital Hamilton population of the pair (i, j) is H_ij rho_ij
+(H symmetric), and its sum over the orbitals i of an atom b is the
+population of the bond between orbital j and atom b.
 """
 import numpy as np
 
@@ -50,3 +56,9 @@ def density_matrix(G, shifts, weights, mu, kT):
     for k in range(G.shape[0]):
         acc += weights[k] * f[k] * np.imag(G[k])
     return -acc / np.pi
+
+
+def cohp(h_col, rho):
+    """Integrated COHP H_ij rho_ij of the listed rows i of one RHS j
+    (h_col[i] = H_ij, rho[i] = rho_ij as density_matrix returns it)."""
+    return np.asarray(h_col, dtype=np.float64) * np.asarray(rho, dtype=np.float64)

@@ -34,7 +34,7 @@ EXPORTS = (
     "scocg_autotune", "scocg_features", "scocg_mlp_nparams", "scocg_mlp_work_floats", "scocg_mlp_forward",
     "scocg_mlp_train_step", "scocg_plan_integrate", "scocg_matrix_from_mtx", "scocg_matrix_shape",
     "scocg_matrix_export_bsr", "scocg_solve_device", "scocg_sync", "scocg_mlp_cfg_default",
-    "scocg_mlp_model_floats", "scocg_mlp_train", "scocg_mlp_predict",
+    "scocg_mlp_model_floats", "scocg_mlp_train", "scocg_mlp_predict", "scocg_plan_cohp",
 )
 
 
@@ -95,6 +95,7 @@ def _declare(lib):
         "scocg_plan_replay": (st, [_VP, _VP]),
         "scocg_features": (st, [_VP, _VP, _VP]),
         "scocg_plan_integrate": (st, [_VP, _VP, _VP, _VP, C.c_double, C.c_double, _VP, _VP]),
+        "scocg_plan_cohp": (st, [_VP, _VP, _VP, _VP]),
         "scocg_mlp_nparams": (i64, []),
         "scocg_mlp_work_floats": (i64, []),
         "scocg_mlp_forward": (st, [_VP, _VP, i64, _VP, _VP]),
@@ -276,6 +277,10 @@ def _sp(stream):
 def scocg_plan_integrate(h, G, weights, mu, kT, rho, ldos=None, stream=None):
     return _check(load().scocg_plan_integrate(h, _sp(stream), _tptr(G), _tptr(weights), float(mu), float(kT),
                                               _tptr(rho), _tptr(ldos)))
+
+
+def scocg_plan_cohp(h, rho, cohp, stream=None):
+    return _check(load().scocg_plan_cohp(h, _sp(stream), _tptr(rho), _tptr(cohp)))
 
 
 def scocg_features(h, feats, stream=None):
@@ -479,16 +484,28 @@ class Plan:
 
     def integrate(self, bufs, weights, mu, kT, stream=None):
         """Density-matrix rows and local DOS from the G of the last run in
-        ``bufs``: returns (rho [out_count] float64, ldos [nrhs, K] float64),
+        ``bufs``: returns (rho [rows] float64, ldos [nrhs, K] float64),
         torch CUDA tensors.  ``weights``: K quadrature weights (array-like)."""
         import torch
         w = torch.as_tensor(np.asarray(weights, dtype=np.float64)).to("cuda")
-        rho = torch.empty(max(1, self.out_count), dtype=torch.float64, device="cuda")
+        rows = int(self.out_offsets[-1])                  # output rows (out_count is rows x K)
+        rho = torch.empty(max(1, rows), dtype=torch.float64, device="cuda")
         ldos = torch.empty((max(1, self.nrhs), self.K), dtype=torch.float64, device="cuda")
         if stream is None:
             stream = torch.cuda.current_stream()
         scocg_plan_integrate(self.h, bufs["out"], w, mu, kT, rho, ldos, stream)
-        return rho[: self.out_count], ldos[: self.nrhs]
+        return rho[:rows], ldos[: self.nrhs]
+
+    def cohp(self, rho, stream=None):
+        """Integrated COHP H_{row(o), j} rho[o] of every output row, from the
+        ``rho`` that ``integrate`` returned (torch CUDA tensor [rows])."""
+        import torch
+        rows = int(self.out_offsets[-1])
+        out = torch.empty(max(1, rows), dtype=torch.float64, device="cuda")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        scocg_plan_cohp(self.h, rho, out, stream)
+        return out[:rows]
 
     def features(self):
         """[nrhs, 16] FP32 features computed on the device (torch tensor)."""

@@ -72,4 +72,21 @@ hipError_t launch_integrate(const double* G, const double* z, const double* w, c
     return hipGetLastError();
 }
 
+// Integrated crystal-orbital Hamilton population of each output pair:
+// cohp[o] = H_{row(o), j} rho[o], with H_{row(o), j} gathered per output row
+// on the host when the plan is built.  Elementwise and bound by HBM.
+__global__ __launch_bounds__(256) void k_cohp(const double* __restrict__ h, const double* __restrict__ rho,
+                                              double* __restrict__ cohp, int64_t n) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        cohp[t] = h[t] * rho[t];
+}
+
+hipError_t launch_cohp(const double* h, const double* rho, double* cohp, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t want = (n + 255) / 256;
+    const int blocks = (int)(want < 8192 ? want : 8192);
+    hipLaunchKernelGGL(k_cohp, dim3(blocks), dim3(256), 0, st, h, rho, cohp, n);
+    return hipGetLastError();
+}
+
 }  // namespace scocg

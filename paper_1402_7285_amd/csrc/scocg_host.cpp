@@ -133,6 +133,7 @@ struct scocg_plan {
     int32_t* degid = nullptr;
     int32_t* doutl = nullptr;
     int64_t* doutoff = nullptr;
+    double* dhout = nullptr;       // H_{row(o), j} of every output row o (scocg_plan_cohp)
     int32_t* dorder = nullptr;
     int32_t* dqueue = nullptr;
     char* dws = nullptr;
@@ -531,6 +532,7 @@ extern "C" void scocg_plan_free(scocg_plan* pl) {
     }
     dev_free(pl->doutl);
     dev_free(pl->doutoff);
+    dev_free(pl->dhout);
     dev_free(pl->dorder);
     dev_free(pl->dqueue);
     dev_free(pl->dws);
@@ -710,6 +712,37 @@ scocg_status build_maps(const scocg_problem* P, int32_t nrhs, const int32_t* rhs
     return SCOCG_OK;
 }
 
+// H_{i, j} for every output row of every RHS (i the output row's global
+// orbital, j the RHS's orbital), from the merged block pattern; 0 where the
+// block (atom(i), atom(j)) is not in the pattern.
+void output_h(const scocg_problem* P, int32_t nrhs, const int32_t* rhs_index, const scocg_rhs_spec* spec,
+              const HostMaps& hm, std::vector<double>& h) {
+    const int bd = P->bd;
+    const bool cluster = spec && spec->cluster_ptr;
+    const bool full = spec && spec->out_mode == SCOCG_OUT_FULL_X;
+    h.assign((size_t)hm.outoff[nrhs], 0.0);
+    auto fn = [&](int64_t r) {
+        const int32_t j = rhs_index[r];
+        const int32_t ja = j / bd, jr = j % bd;
+        const int64_t n = hm.outoff[r + 1] - hm.outoff[r];
+        double* hr = h.data() + hm.outoff[r];
+        for (int64_t t = 0; t < n; ++t) {
+            int64_t i;
+            if (!full) i = spec->out_rows[spec->out_ptr[r] + t];
+            else if (cluster) i = (int64_t)spec->cluster_atoms[spec->cluster_ptr[r] + t / bd] * bd + t % bd;
+            else i = t;
+            const int64_t ia = i / bd;
+            const int32_t* beg = P->col.data() + P->rowptr[ia];
+            const int32_t* end = P->col.data() + P->rowptr[ia + 1];
+            const int32_t* f = std::lower_bound(beg, end, ja);
+            if (f == end || *f != ja) continue;
+            const int64_t e = f - P->col.data();
+            hr[t] = P->hH[(size_t)e * bd * bd + (size_t)(i % bd) * bd + jr];
+        }
+    };
+    parallel_for(nrhs, fn);
+}
+
 }  // namespace
 
 extern "C" scocg_status scocg_plan_create(scocg_problem* P, const scocg_options* opt_in, int32_t nshift,
@@ -832,6 +865,11 @@ extern "C" scocg_status scocg_plan_create(scocg_problem* P, const scocg_options*
     }
     if ((st = dev_upload(&pl->doutl, hm.outl.data(), hm.outl.size()))) return bail(st);
     if ((st = dev_upload(&pl->doutoff, hm.outoff.data(), hm.outoff.size()))) return bail(st);
+    {
+        std::vector<double> hout;
+        output_h(P, nrhs, rhs_index, spec, hm, hout);
+        if ((st = dev_upload(&pl->dhout, hout.data(), hout.size()))) return bail(st);
+    }
     if ((st = dev_upload(&pl->dorder, order.data(), order.size()))) return bail(st);
     if (hipMalloc((void**)&pl->dqueue, sizeof(int32_t)) != hipSuccess) return bail(fail(SCOCG_E_NOMEM, "queue"));
     if (nrhs > 0) {
@@ -940,6 +978,15 @@ extern "C" scocg_status scocg_plan_integrate(scocg_plan* pl, void* stream, const
     (void)hipGetLastError();
     HIP_TRY(scocg::launch_integrate((const double*)G, pl->dz, weights, pl->drhs, pl->doutoff, pl->doutl, pl->nrhs,
                                     pl->K, mu, kT, rho, ldos, st));
+    return SCOCG_OK;
+}
+
+extern "C" scocg_status scocg_plan_cohp(scocg_plan* pl, void* stream, const double* rho, double* cohp) {
+    if (!pl || !rho || !cohp) return fail(SCOCG_E_ARG, "NULL argument");
+    if (pl->nrhs == 0) return SCOCG_OK;
+    HIP_TRY(hipSetDevice(pl->P->device));
+    (void)hipGetLastError();
+    HIP_TRY(scocg::launch_cohp(pl->dhout, rho, cohp, pl->out_off[pl->nrhs], (hipStream_t)stream));
     return SCOCG_OK;
 }
 

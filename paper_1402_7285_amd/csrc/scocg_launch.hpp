@@ -25,5 +25,6 @@ hipError_t launch_qmr(const KParams& P, int bd, bool sid, bool gal, int nt, int 
 hipError_t launch_integrate(const double* G, const double* z, const double* w, const RhsInfo* rhs,
                             const int64_t* out_off, const int32_t* out_local, int nrhs, int K, double mu, double kT,
                             double* rho, double* ldos, hipStream_t st);
+hipError_t launch_cohp(const double* h, const double* rho, double* cohp, int64_t n, hipStream_t st);
 
 }  // namespace scocg

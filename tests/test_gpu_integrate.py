@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from oracle import dense_solve, integrate as I, local_system
-from synth import bsr_to_scipy, make_config, make_problem
+from synth import bsr_to_dense, bsr_to_scipy, make_config, make_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -95,3 +95,62 @@ def test_integrate_full_x_and_missing_diagonal(B):
     # arguments
     with pytest.raises(B.ScocgError):
         plan.integrate(bufs, w, 0.0, -1.0)
+
+
+@pytest.mark.parametrize("case", ["cfg0", "clusters", "clusters_full_x"])
+def test_cohp_matches_oracle(B, case):
+    """GPU COHP = H_{row, j} rho per output row, against the oracle's product
+    on the GPU's own rho (only the H lookup and the layout can differ, so
+    the match is exact); the rows' global orbitals follow the output mode."""
+    if case == "cfg0":
+        prob = make_config(0)
+        kw = {}
+    else:
+        prob = make_problem(name="fcc3-clusters", lattice="fcc", L=3, bdim=9, hop=(0.0, 0.5), s_scale=0.03,
+                            K=12, eta=0.05, nrhs=6, radius=(1.0, 1.6), seed_key=(6, 6, 6))
+        kw = dict(full_x=True) if case.endswith("full_x") else {}
+    w = I.trapezoid_weights(prob.shifts.real)
+    P, plan, bufs = _run(B, prob, **kw)
+    rho_d, _ = plan.integrate(bufs, w, 0.1, 0.2)
+    cohp = plan.cohp(rho_d).cpu().numpy()
+    rho = rho_d.cpu().numpy()
+    off = plan.out_offsets
+    Hd = bsr_to_scipy(prob.H).tocsc()
+    bd = prob.H.bdim
+    nonzero = 0
+    for j in range(prob.nrhs):
+        if case == "clusters_full_x":
+            at = prob.cluster_atoms[prob.cluster_ptr[j]:prob.cluster_ptr[j + 1]]
+            rows = (at[:, None] * bd + np.arange(bd)[None, :]).ravel()
+        else:
+            rows = prob.outs(j)
+        h = Hd[:, int(prob.rhs[j])].toarray().ravel()[rows]
+        want = I.cohp(h, rho[off[j]:off[j + 1]])
+        got = cohp[off[j]:off[j + 1]]
+        assert got.shape == want.shape
+        assert np.array_equal(got, want), (case, j, np.abs(got - want).max())
+        nonzero += int(np.count_nonzero(got))
+    assert nonzero > 0
+    print(f"[cohp] {case}: {cohp.size} rows, {nonzero} nonzero pair populations, equal to the oracle", flush=True)
+
+
+def test_cohp_sum_rule_full_x(B):
+    """Summed over every row of a FULL_X output, the COHP of RHS j is
+    (H rho)_jj, which the eigen-expansion gives without G."""
+    prob = make_config(0, nrhs=3)
+    w = I.trapezoid_weights(prob.shifts.real)
+    mu, kT = 0.2, 0.3
+    P, plan, bufs = _run(B, prob, full_x=True)
+    rho_d, _ = plan.integrate(bufs, w, mu, kT)
+    cohp = plan.cohp(rho_d).cpu().numpy()
+    Hd = bsr_to_dense(prob.H)
+    eps, Y = np.linalg.eigh(Hd)                  # S = I here
+    E, eta = prob.shifts.real, prob.shifts.imag[0]
+    L = (eta / np.pi) / ((E[:, None] - eps[None, :]) ** 2 + eta ** 2)
+    c = (w * I.fermi(E, mu, kT)) @ L
+    off = plan.out_offsets
+    for j in range(prob.nrhs):
+        jj = int(prob.rhs[j])
+        band_jj = np.sum(c * eps * Y[jj, :] ** 2)
+        got = cohp[off[j]:off[j + 1]].sum()
+        assert abs(got - band_jj) <= 1e-6 * max(1.0, abs(band_jj)), (j, got, band_jj)

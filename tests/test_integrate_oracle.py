@@ -74,3 +74,36 @@ def test_density_matrix_tends_to_occupied_projector():
     want = (Y * (Y[j, :] * (eps < mu))[None, :]).sum(axis=1)
     # Lorentzian tails of half-width eta cost O(eta / gap) and O(eta / 4) at the mesh ends
     assert np.abs(rho - want).max() < 0.05
+
+
+@pytest.mark.parametrize("kT", [0.0, 0.25])
+def test_cohp_sum_rule_and_bonds_against_eigen_expansion(kT):
+    """Sum over every row i of H_ij rho_ij is (H rho)_jj = sum_n c_n eps_n
+    (S y_n)_j y_jn (from H y_n = eps_n S y_n), and the sum over one atom's
+    orbitals is sum_{i in b} H_ij sum_n c_n y_in y_jn, both without forming
+    G; c_n is the quadrature of f times the Lorentzian of eigenvalue n."""
+    p = _small(True)
+    Hd, Sd = bsr_to_dense(p.H), bsr_to_dense(p.S)
+    eps, Y = sla.eigh(Hd, Sd)
+    E = p.shifts.real
+    eta = p.shifts.imag[0]
+    w = I.trapezoid_weights(E)
+    mu = -0.3
+    f = I.fermi(E, mu, kT)
+    L = (eta / np.pi) / ((E[:, None] - eps[None, :]) ** 2 + eta ** 2)
+    c = (w * f) @ L
+    SY = Sd @ Y
+    bd = p.H.bdim
+    for j in p.rhs:
+        b = np.zeros(p.M)
+        b[j] = 1.0
+        G = np.stack([dense_solve(Hd, Sd, z, b) for z in p.shifts])
+        rho = I.density_matrix(G, p.shifts, w, mu, kT)
+        pop = I.cohp(Hd[:, j], rho)
+        band_jj = np.sum(c * eps * SY[j, :] * Y[j, :])
+        assert np.isclose(pop.sum(), band_jj, rtol=1e-9, atol=1e-12)
+        # the bond between orbital j and each neighbouring atom
+        for a in {int(i) // bd for i in np.nonzero(Hd[:, j])[0]}:
+            rows = np.arange(a * bd, (a + 1) * bd)
+            want = np.sum(Hd[rows, j] * (Y[rows, :] @ (c * Y[j, :])))
+            assert np.isclose(pop[rows].sum(), want, rtol=1e-9, atol=1e-12)
