@@ -9,7 +9,7 @@ bound ||x - x*|| <= ||A^-1||_2 ||b - A x|| with ||A^-1||_2 <= 1/(|Im z| lam_min(
 less 1%.  The solver stops when its residual estimate is below tol; the
 estimate and the true residual agree far below tol in FP64, so twice tol
 is used as the residual.  The launch configuration is the one the benchmark
-times (projected FP64 form, 1024-thread workgroups).
+times (1024-thread workgroups, 256 resident), in both solver forms it times.
 """
 import numpy as np
 import pytest
@@ -68,23 +68,30 @@ def _check_sampled(prob, r, shifts_idx, tol, full_x=False, label=""):
     return worst_rel
 
 
-def test_cfg1_full_size_sampled(B):
+FORMS = {"seed-switching projected": 0, "Lanczos-basis": 2}
+
+
+@pytest.mark.parametrize("form", sorted(FORMS))
+def test_cfg1_full_size_sampled(B, form):
     """Configuration 1 at full size (M = 16,384, 128 shifts), four RHS spread
-    over the index set, the benchmark's launch shape; two sampled shifts
-    (band centre and band edge) against sparse LU."""
+    over the index set, the benchmark's launch shape (the Lanczos-basis form
+    is the one the benchmark reports, the seed-switching form its companion);
+    two sampled shifts (band centre and band edge) against sparse LU."""
     full = make_config(1)
     prob = full.subset([0, 85, 170, 255])
     tol = 1e-6
-    P, plan = _plan(B, prob, tol=tol, threads=1024, slots=256)
-    assert plan.info["global"] & 2 and plan.info["threads"] == 1024
+    P, plan = _plan(B, prob, tol=tol, threads=1024, slots=256, method=FORMS[form])
+    assert plan.info["threads"] == 1024
+    assert plan.info["global"] & (8 if FORMS[form] == 2 else 2)
     r = plan.solve()
     assert np.all(r["status"] == CONVERGED)
     assert np.all(r["resid"] <= tol)
     K = prob.nshift
-    _check_sampled(prob, r, [K // 2, K - 1], tol, label="cfg1 projected FP64")
+    _check_sampled(prob, r, [K // 2, K - 1], tol, label=f"cfg1 {form} FP64")
 
 
-def test_cfg2_full_size_smallest_clusters(B):
+@pytest.mark.parametrize("form", sorted(FORMS))
+def test_cfg2_full_size_smallest_clusters(B, form):
     """Configuration 2's matrices at full size (fcc 32^3, M = 1,179,648, 256
     shifts); the two RHS with the smallest clusters (M_j = 1,269) of the first
     64, every eighth shift and the last against sparse LU of the local
@@ -96,10 +103,10 @@ def test_cfg2_full_size_smallest_clusters(B):
     pick = np.argsort(sizes, kind="stable")[:2]
     prob = full.subset(pick)
     tol = 1e-6
-    P, plan = _plan(B, prob, tol=tol)
-    assert plan.info["global"] & 2
+    P, plan = _plan(B, prob, tol=tol, method=FORMS[form])
+    assert plan.info["global"] & (8 if FORMS[form] == 2 else 2)
     r = plan.solve()
     assert np.all(r["status"] == CONVERGED)
     assert np.all(r["resid"] <= tol)
     every = list(range(0, prob.nshift, 8)) + [prob.nshift - 1]
-    _check_sampled(prob, r, every, tol, label="cfg2 projected FP64")
+    _check_sampled(prob, r, every, tol, label=f"cfg2 {form} FP64")
