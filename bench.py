@@ -497,6 +497,7 @@ def main():
         "config": {"workload": f"{args.workload}: {wl['desc']}", "nrhs": prob.nrhs, "shifts": prob.nshift,
                    "M": prob.M, "tol": args.tol, "precision": args.precision, "batched": "persistent",
                    "slots": plan.info["slots"], "threads": plan.info["threads"], "form": r["form"],
+                   "lds_bytes": plan.info["lds_bytes"], "cg_direction_in_lds": bool(plan.info["global"] & 16),
                    "autotuned": r["autotuned"]},
         **r["report"],
     }

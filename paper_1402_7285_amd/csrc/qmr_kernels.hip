@@ -77,6 +77,10 @@ __host__ __device__ inline size_t lds_bytes(int K, int NT) {
     return b;
 }
 
+// Offset of the inner CG's search direction when it is kept in LDS (DL):
+// after the per-shift arrays, M_j doubles.
+__host__ __device__ inline size_t lds_dir_offset(int K, int NT) { return (lds_bytes(K, NT) + 15) & ~(size_t)15; }
+
 __device__ inline Lds carve(unsigned char* q, int K, int NT) {
     Lds L;
     L.s1 = (zc*)q; q += sizeof(zc) * K;
@@ -235,8 +239,11 @@ __host__ __device__ inline int64_t slot_bytes(int K, int64_t Mp, int64_t nIp) {
     return ((8 * Mp) * 8 + 3 * (int64_t)K * nIp * 16 + 255) / 256 * 256;
 }
 
-template <int BD, int NT, bool SID, bool GAL>
-__device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
+// DL: the inner CG's search direction d lives in LDS (ldsd, M_j doubles)
+// instead of the workgroup's HBM slot, so the sparse product on S gathers it
+// from LDS and the CG's vector passes touch one vector fewer in HBM.
+template <int BD, int NT, bool SID, bool GAL, bool DL>
+__device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L, double* ldsd) {
     const int tid = threadIdx.x;
     const int K = P.K;
     const RhsInfo ri = P.rhs[rj];
@@ -260,8 +267,8 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
     double* tA = wB + Mp;
     double* q = tA + Mp;
     double* res = q + Mp;
-    double* d = res + Mp;
-    double* wcg = d + Mp;
+    double* d = DL ? ldsd : res + Mp;
+    double* wcg = res + 2 * Mp;
     double2* xI = (double2*)(wcg + Mp);
     double2* D0 = xI + (int64_t)K * nIp;
     double2* D1 = D0 + (int64_t)K * nIp;
@@ -519,11 +526,12 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
     __syncthreads();
 }
 
-template <int BD, int NT, bool SID, bool GAL>
+template <int BD, int NT, bool SID, bool GAL, bool DL>
 __global__ __launch_bounds__(NT) void k_sqmr(KParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_job;
     const Lds L = carve(smem, P.K, NT);
+    double* ldsd = DL ? (double*)(smem + lds_dir_offset(P.K, NT)) : nullptr;
     char* ws = P.ws + (int64_t)blockIdx.x * P.slot_bytes;
     for (;;) {
         if (threadIdx.x == 0) {
@@ -534,41 +542,47 @@ __global__ __launch_bounds__(NT) void k_sqmr(KParams P) {
         const int job = s_job;
         __syncthreads();
         if (job >= P.nrhs) break;
-        solve_one<BD, NT, SID, GAL>(P, P.order[job], ws, L);
+        solve_one<BD, NT, SID, GAL, DL>(P, P.order[job], ws, L, ldsd);
     }
 }
 
 template <int BD, int NT>
-static hipError_t launch_nt(const KParams& P, bool sid, bool gal, int slots, hipStream_t st) {
+static hipError_t launch_nt(const KParams& P, bool sid, bool gal, bool dl, int slots, hipStream_t st) {
     const size_t lds = lds_bytes(P.K, NT);
     if (gal) {
-        if (sid) hipLaunchKernelGGL((k_sqmr<BD, NT, true, true>), dim3(slots), dim3(NT), lds, st, P);
-        else hipLaunchKernelGGL((k_sqmr<BD, NT, false, true>), dim3(slots), dim3(NT), lds, st, P);
+        if (sid) hipLaunchKernelGGL((k_sqmr<BD, NT, true, true, false>), dim3(slots), dim3(NT), lds, st, P);
+        else if (dl)
+            hipLaunchKernelGGL((k_sqmr<BD, NT, false, true, true>), dim3(slots), dim3(NT),
+                               lds_dir_offset(P.K, NT) + sizeof(double) * (size_t)P.Mp, st, P);
+        else hipLaunchKernelGGL((k_sqmr<BD, NT, false, true, false>), dim3(slots), dim3(NT), lds, st, P);
     } else {
-        if (sid) hipLaunchKernelGGL((k_sqmr<BD, NT, true, false>), dim3(slots), dim3(NT), lds, st, P);
-        else hipLaunchKernelGGL((k_sqmr<BD, NT, false, false>), dim3(slots), dim3(NT), lds, st, P);
+        if (sid) hipLaunchKernelGGL((k_sqmr<BD, NT, true, false, false>), dim3(slots), dim3(NT), lds, st, P);
+        else hipLaunchKernelGGL((k_sqmr<BD, NT, false, false, false>), dim3(slots), dim3(NT), lds, st, P);
     }
     return hipGetLastError();
 }
 
 template <int BD>
-static hipError_t launch_bd(const KParams& P, bool sid, bool gal, int nt, int slots, hipStream_t st) {
-    if (nt == 256) return launch_nt<BD, 256>(P, sid, gal, slots, st);
-    if (nt == 1024) return launch_nt<BD, 1024>(P, sid, gal, slots, st);
-    return launch_nt<BD, 512>(P, sid, gal, slots, st);
+static hipError_t launch_bd(const KParams& P, bool sid, bool gal, bool dl, int nt, int slots, hipStream_t st) {
+    if (nt == 256) return launch_nt<BD, 256>(P, sid, gal, dl, slots, st);
+    if (nt == 1024) return launch_nt<BD, 1024>(P, sid, gal, dl, slots, st);
+    return launch_nt<BD, 512>(P, sid, gal, dl, slots, st);
 }
 
 }  // namespace qmr
 
-size_t qmr_lds_bytes(int K, int nt) { return qmr::lds_bytes(K, nt); }
+size_t qmr_lds_bytes(int K, int nt, int64_t Mp, bool dl) {
+    return dl ? qmr::lds_dir_offset(K, nt) + sizeof(double) * (size_t)Mp : qmr::lds_bytes(K, nt);
+}
 
 int64_t qmr_slot_bytes(int K, int64_t Mp, int64_t nIp) { return qmr::slot_bytes(K, Mp, nIp); }
 
-hipError_t launch_qmr(const KParams& P, int bd, bool sid, bool gal, int nt, int slots, hipStream_t st) {
+hipError_t launch_qmr(const KParams& P, int bd, bool sid, bool gal, bool dl, int nt, int slots, hipStream_t st) {
+    if (dl && (sid || !gal)) return hipErrorInvalidValue;      // built for the generalized Lanczos-COCG form only
     switch (bd) {
-        case 1: return qmr::launch_bd<1>(P, sid, gal, nt, slots, st);
-        case 4: return qmr::launch_bd<4>(P, sid, gal, nt, slots, st);
-        case 9: return qmr::launch_bd<9>(P, sid, gal, nt, slots, st);
+        case 1: return qmr::launch_bd<1>(P, sid, gal, dl, nt, slots, st);
+        case 4: return qmr::launch_bd<4>(P, sid, gal, dl, nt, slots, st);
+        case 9: return qmr::launch_bd<9>(P, sid, gal, dl, nt, slots, st);
         default: return hipErrorInvalidValue;
     }
 }

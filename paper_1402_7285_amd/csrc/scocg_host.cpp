@@ -121,6 +121,7 @@ struct scocg_plan {
     bool proj = false;        // projected (requested rows only) FP64 solve
     bool qmr = false;         // real S-Lanczos basis (QMR, or the COCG iterates if gal)
     bool gal = false;
+    bool dl = false;          // Lanczos-COCG with the inner CG's direction in LDS
     int64_t nIp = 0;
     int64_t Mp = 0, slot_bytes = 0, out_count = 0;
     std::vector<int64_t> out_off;
@@ -828,7 +829,10 @@ extern "C" scocg_status scocg_plan_create(scocg_problem* P, const scocg_options*
     auto bail = [&](scocg_status e) { scocg_plan_free(pl); return e; };
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess || cus <= 0) cus = 256;
-    const size_t lds = pl->qmr ? scocg::qmr_lds_bytes(nshift, pl->nt) : scocg::solver_lds_bytes(nshift, pl->nt);
+    // the generalized Lanczos-COCG form keeps the inner CG's direction in LDS when it fits
+    pl->dl = pl->gal && P->has_S && scocg::qmr_lds_bytes(nshift, pl->nt, pl->Mp, true) <= 160 * 1024;
+    const size_t lds = pl->qmr ? scocg::qmr_lds_bytes(nshift, pl->nt, pl->Mp, pl->dl)
+                               : scocg::solver_lds_bytes(nshift, pl->nt);
     if (lds > 160 * 1024) return bail(fail(SCOCG_E_UNSUPPORTED, "too many shifts for LDS"));
     int per_cu = std::max(1, 2048 / pl->nt);
     per_cu = std::min<int>(per_cu, (int)std::max<size_t>(1, (160 * 1024) / lds));
@@ -891,9 +895,10 @@ extern "C" scocg_status scocg_plan_info(const scocg_plan* pl, int64_t* info) {
     info[2] = pl->Mp;
     info[3] = pl->slot_bytes;
     info[4] = pl->seed0;
-    info[5] = (int64_t)(pl->qmr ? scocg::qmr_lds_bytes(pl->K, pl->nt) : scocg::solver_lds_bytes(pl->K, pl->nt));
+    info[5] = (int64_t)(pl->qmr ? scocg::qmr_lds_bytes(pl->K, pl->nt, pl->Mp, pl->dl)
+                                : scocg::solver_lds_bytes(pl->K, pl->nt));
     info[6] = pl->prec;
-    info[7] = (pl->global ? 1 : 0) | (pl->proj ? 2 : 0) | (pl->qmr ? 4 : 0) | (pl->gal ? 8 : 0);
+    info[7] = (pl->global ? 1 : 0) | (pl->proj ? 2 : 0) | (pl->qmr ? 4 : 0) | (pl->gal ? 8 : 0) | (pl->dl ? 16 : 0);
     return SCOCG_OK;
 }
 
@@ -963,7 +968,7 @@ extern "C" scocg_status scocg_plan_run(scocg_plan* pl, void* stream, scocg_z* ou
     KParams k = make_kparams(pl, out, iters, status, resid);
     (void)hipGetLastError();   // drop any error another caller left on this thread
     HIP_TRY(scocg::launch_fill_i32(pl->dqueue, 0, 1, st));
-    if (pl->qmr) HIP_TRY(scocg::launch_qmr(k, P->bd, !P->has_S, pl->gal, pl->nt, pl->slots, st));
+    if (pl->qmr) HIP_TRY(scocg::launch_qmr(k, P->bd, !P->has_S, pl->gal, pl->dl, pl->nt, pl->slots, st));
     else HIP_TRY(scocg::launch_solver(k, P->bd, pl->proj ? 3 : pl->prec, !P->has_S, pl->nt, pl->slots, st));
     return SCOCG_OK;
 }

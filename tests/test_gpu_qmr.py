@@ -73,6 +73,8 @@ def test_cocg_on_lanczos_basis_parity(B, case, threads):
     prob = CASES[case]()
     P, plan = _plan(B, prob, method=B.METHOD_COCG_LANCZOS, threads=threads)
     assert plan.info["global"] & 8
+    # with S != I the inner CG's direction is kept in LDS (it fits at these sizes)
+    assert bool(plan.info["global"] & 16) == (prob.S is not None)
     r = plan.solve()
     Hcsr = bsr_to_scipy(prob.H)
     Scsr = bsr_to_scipy(prob.S) if prob.S is not None else None
