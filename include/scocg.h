@@ -246,8 +246,8 @@ int64_t scocg_plan_out_count(const scocg_plan* plan);
  * one slot, [4] initial seed index, [5] LDS bytes per workgroup,
  * [6] precision, [7] bit 0: every RHS uses the whole system; bit 1: projected;
  * bit 2: a real Lanczos-basis method; bit 3: its COCG (Galerkin) iterates;
- * bit 4: the inner CG's direction vector is kept in LDS (Lanczos-COCG with
- * S != I, when M_j doubles fit beside the per-shift arrays).
+ * bit 4: the inner CG's direction vector is kept in LDS (a Lanczos-basis
+ * method with S != I, when M_j doubles fit beside the per-shift arrays).
  */
 #define SCOCG_NINFO 8
 scocg_status scocg_plan_info(const scocg_plan* plan, int64_t* info);

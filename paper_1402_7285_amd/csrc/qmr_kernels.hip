@@ -557,6 +557,9 @@ static hipError_t launch_nt(const KParams& P, bool sid, bool gal, bool dl, int s
         else hipLaunchKernelGGL((k_sqmr<BD, NT, false, true, false>), dim3(slots), dim3(NT), lds, st, P);
     } else {
         if (sid) hipLaunchKernelGGL((k_sqmr<BD, NT, true, false, false>), dim3(slots), dim3(NT), lds, st, P);
+        else if (dl)
+            hipLaunchKernelGGL((k_sqmr<BD, NT, false, false, true>), dim3(slots), dim3(NT),
+                               lds_dir_offset(P.K, NT) + sizeof(double) * (size_t)P.Mp, st, P);
         else hipLaunchKernelGGL((k_sqmr<BD, NT, false, false, false>), dim3(slots), dim3(NT), lds, st, P);
     }
     return hipGetLastError();
@@ -578,7 +581,7 @@ size_t qmr_lds_bytes(int K, int nt, int64_t Mp, bool dl) {
 int64_t qmr_slot_bytes(int K, int64_t Mp, int64_t nIp) { return qmr::slot_bytes(K, Mp, nIp); }
 
 hipError_t launch_qmr(const KParams& P, int bd, bool sid, bool gal, bool dl, int nt, int slots, hipStream_t st) {
-    if (dl && (sid || !gal)) return hipErrorInvalidValue;      // built for the generalized Lanczos-COCG form only
+    if (dl && sid) return hipErrorInvalidValue;      // no inner CG when S = I
     switch (bd) {
         case 1: return qmr::launch_bd<1>(P, sid, gal, dl, nt, slots, st);
         case 4: return qmr::launch_bd<4>(P, sid, gal, dl, nt, slots, st);

@@ -829,8 +829,8 @@ extern "C" scocg_status scocg_plan_create(scocg_problem* P, const scocg_options*
     auto bail = [&](scocg_status e) { scocg_plan_free(pl); return e; };
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess || cus <= 0) cus = 256;
-    // the generalized Lanczos-COCG form keeps the inner CG's direction in LDS when it fits
-    pl->dl = pl->gal && P->has_S && scocg::qmr_lds_bytes(nshift, pl->nt, pl->Mp, true) <= 160 * 1024;
+    // the generalized Lanczos-basis forms keep the inner CG's direction in LDS when it fits
+    pl->dl = pl->qmr && P->has_S && scocg::qmr_lds_bytes(nshift, pl->nt, pl->Mp, true) <= 160 * 1024;
     const size_t lds = pl->qmr ? scocg::qmr_lds_bytes(nshift, pl->nt, pl->Mp, pl->dl)
                                : scocg::solver_lds_bytes(nshift, pl->nt);
     if (lds > 160 * 1024) return bail(fail(SCOCG_E_UNSUPPORTED, "too many shifts for LDS"));

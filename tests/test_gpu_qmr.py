@@ -48,6 +48,7 @@ def test_qmr_parity(B, case, threads):
     prob = CASES[case]()
     P, plan = _plan(B, prob, threads=threads)
     assert plan.info["global"] & 4
+    assert bool(plan.info["global"] & 16) == (prob.S is not None)
     r = plan.solve()
     Hcsr = bsr_to_scipy(prob.H)
     Scsr = bsr_to_scipy(prob.S) if prob.S is not None else None
