@@ -43,7 +43,8 @@ enum { ST_CONVERGED = 0, ST_MAXITER = 1, ST_BREAKDOWN = 2, ST_NONFINITE = 3 };
 struct Sys {
     const int64_t* rowptr;
     const int32_t* ecol;
-    const int32_t* egid;
+    const int32_t* egid;   // nullptr: entry e holds block gbase + e (the global system)
+    int64_t gbase;
     int nrows;
     int M;
 };
@@ -108,14 +109,16 @@ __device__ inline Lds carve(unsigned char* q, int K, int NT) {
 // vector loads of the chunk, then the arithmetic; a chunk's slots past the
 // row's end re-read its last entry and add zero (every block row holds its
 // diagonal block).  4x4 blocks: the quad of lanes of one block row shares
-// the vector block by DPP.
+// the vector block by DPP.  DIRECT (the global system, entry e holds block
+// e): the block loads need no block index, so they go out with the column
+// index loads and a chunk waits on one dependent load instead of two.
 template <int BD, int NT>
 struct Chunk {
     static constexpr int v = (BD == 1 ? 8 : (BD <= 4 ? 4 : 2)) / (NT >= 1024 ? 2 : 1);
     static constexpr int value = v < 1 ? 1 : v;
 };
 
-template <int BD, int NT>
+template <int BD, int NT, bool DIRECT>
 __device__ __forceinline__ double row_dot(const double* __restrict__ A, const Sys& sy, int a, int r,
                                           const double* __restrict__ p) {
     constexpr int CH = Chunk<BD, NT>::value;
@@ -123,20 +126,21 @@ __device__ __forceinline__ double row_dot(const double* __restrict__ A, const Sy
     const int64_t e0 = sy.rowptr[a], e1 = sy.rowptr[a + 1];
     double acc = 0.0;
     for (int64_t eb = e0; eb < e1; eb += CH) {
-        int32_t b[CH], g[CH];
+        int32_t b[CH];
+        int64_t g[CH];
         bool ok[CH];
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
             ok[u] = eb + u < e1;
             const int64_t e = ok[u] ? eb + u : e1 - 1;
             b[u] = sy.ecol[e];
-            g[u] = sy.egid[e];
+            g[u] = DIRECT ? sy.gbase + e : (int64_t)sy.egid[e];
         }
         double own[QUAD ? CH : 1];
         double av[CH][BD];
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
-            const int64_t off = ((int64_t)g[u] * BD + r) * BD;
+            const int64_t off = (g[u] * BD + r) * BD;
             if constexpr (QUAD) own[u] = p[(int64_t)b[u] * BD + r];
 #pragma unroll
             for (int c = 0; c < BD; ++c) av[u][c] = A[off + c];
@@ -163,17 +167,24 @@ __device__ __forceinline__ double row_dot(const double* __restrict__ A, const Sy
 }
 
 // y = A x over this thread's rows; returns the partial x^T y.
-template <int BD, int NT>
-__device__ __forceinline__ double spmv(const double* __restrict__ A, const Sys& sy, const double* __restrict__ x,
-                                       double* __restrict__ y) {
+template <int BD, int NT, bool DIRECT>
+__device__ __forceinline__ double spmv_rows(const double* __restrict__ A, const Sys& sy,
+                                            const double* __restrict__ x, double* __restrict__ y) {
     double part = 0.0;
     for (int i = threadIdx.x; i < sy.M; i += NT) {
         const int a = i / BD, r = i - a * BD;
-        const double v = row_dot<BD, NT>(A, sy, a, r, x);
+        const double v = row_dot<BD, NT, DIRECT>(A, sy, a, r, x);
         y[i] = v;
         part += x[i] * v;
     }
     return part;
+}
+
+template <int BD, int NT>
+__device__ __forceinline__ double spmv(const double* __restrict__ A, const Sys& sy, const double* __restrict__ x,
+                                       double* __restrict__ y) {
+    if (sy.egid == nullptr) return spmv_rows<BD, NT, true>(A, sy, x, y);
+    return spmv_rows<BD, NT, false>(A, sy, x, y);
 }
 
 // Solve S q = t (real SPD S, real vectors) by CG from 0 to ||res|| <= tol ||t||;
@@ -251,7 +262,8 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L, doub
     Sys sy;
     sy.rowptr = P.rowptr_l + si.row_base;
     sy.ecol = P.ecol + si.ent_base;
-    sy.egid = P.egid + si.ent_base;
+    sy.egid = P.ent_direct ? nullptr : P.egid + si.ent_base;
+    sy.gbase = si.ent_base;
     sy.nrows = si.nrows;
     sy.M = si.nrows * BD;
     const int M = sy.M;

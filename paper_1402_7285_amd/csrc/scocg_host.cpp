@@ -943,6 +943,7 @@ static KParams make_kparams(const scocg_plan* pl, scocg_z* out, int32_t* iters, 
     k.replace_every = pl->opt.replace_every;
     k.audit = pl->opt.audit;
     k.s_unit_diag = P->s_unit_diag ? 1 : 0;
+    k.ent_direct = pl->global ? 1 : 0;     // the global system's egid is dIota
     k.queue = pl->dqueue;
     k.ws = pl->dws;
     k.slot_bytes = pl->slot_bytes;

@@ -52,6 +52,7 @@ struct KParams {
     int32_t replace_every;     // FP32 forms
     int32_t audit;             // FP32 forms
     int32_t s_unit_diag;       // S's diagonal blocks are exactly I
+    int32_t ent_direct;        // egid is the identity: entry e holds block e
     // work queue and per-workgroup memory
     int32_t* queue;            // next RHS to hand out
     char* ws;
