@@ -247,7 +247,10 @@ int64_t scocg_plan_out_count(const scocg_plan* plan);
  * [6] precision, [7] bit 0: every RHS uses the whole system; bit 1: projected;
  * bit 2: a real Lanczos-basis method; bit 3: its COCG (Galerkin) iterates;
  * bit 4: the inner CG's direction vector is kept in LDS (a Lanczos-basis
- * method with S != I, when M_j doubles fit beside the per-shift arrays).
+ * method with S != I, when M_j doubles fit beside the per-shift arrays);
+ * bit 5: with bit 4 on a global system whose S has exactly-identity
+ * diagonal blocks, S is applied as I plus a plan-held copy of its nonzero
+ * off-diagonal blocks.
  */
 #define SCOCG_NINFO 8
 scocg_status scocg_plan_info(const scocg_plan* plan, int64_t* info);

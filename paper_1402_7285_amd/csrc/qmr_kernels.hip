@@ -166,30 +166,37 @@ __device__ __forceinline__ double row_dot(const double* __restrict__ A, const Sy
     return acc;
 }
 
-// y = A x over this thread's rows; returns the partial x^T y.
-template <int BD, int NT, bool DIRECT>
+// y = A x over this thread's rows; returns the partial x^T y.  UNIT: A is
+// I plus the blocks of sy (S with exactly-identity diagonal blocks, its
+// off-diagonal blocks alone in sy), so the identity part is x_i itself.
+template <int BD, int NT, bool DIRECT, bool UNIT>
 __device__ __forceinline__ double spmv_rows(const double* __restrict__ A, const Sys& sy,
                                             const double* __restrict__ x, double* __restrict__ y) {
     double part = 0.0;
     for (int i = threadIdx.x; i < sy.M; i += NT) {
         const int a = i / BD, r = i - a * BD;
-        const double v = row_dot<BD, NT, DIRECT>(A, sy, a, r, x);
+        const double xi = x[i];
+        const double v = row_dot<BD, NT, DIRECT>(A, sy, a, r, x) + (UNIT ? xi : 0.0);
         y[i] = v;
-        part += x[i] * v;
+        part += xi * v;
     }
     return part;
 }
 
-template <int BD, int NT>
+template <int BD, int NT, bool UNIT = false>
 __device__ __forceinline__ double spmv(const double* __restrict__ A, const Sys& sy, const double* __restrict__ x,
                                        double* __restrict__ y) {
-    if (sy.egid == nullptr) return spmv_rows<BD, NT, true>(A, sy, x, y);
-    return spmv_rows<BD, NT, false>(A, sy, x, y);
+    if constexpr (UNIT) {
+        return spmv_rows<BD, NT, true, true>(A, sy, x, y);        // off-diagonal copy: entry e is block e
+    } else {
+        if (sy.egid == nullptr) return spmv_rows<BD, NT, true, false>(A, sy, x, y);
+        return spmv_rows<BD, NT, false, false>(A, sy, x, y);
+    }
 }
 
 // Solve S q = t (real SPD S, real vectors) by CG from 0 to ||res|| <= tol ||t||;
 // tt = ||t||^2 (already reduced).  Returns the iteration count.
-template <int BD, int NT>
+template <int BD, int NT, bool UNIT>
 __device__ int inner_cg(const double* __restrict__ S, const Sys& sy, const double* __restrict__ t,
                         double* __restrict__ q, double* __restrict__ res, double* __restrict__ d,
                         double* __restrict__ w, double tt, double tol, int maxit, double* red) {
@@ -205,7 +212,7 @@ __device__ int inner_cg(const double* __restrict__ S, const Sys& sy, const doubl
     double rr = tt;
     int it = 0;
     while (it < maxit && !(sqrt(rr) <= stop)) {
-        double dw[1] = {spmv<BD, NT>(S, sy, d, w)};
+        double dw[1] = {spmv<BD, NT, UNIT>(S, sy, d, w)};
         block_sum<NT, 1>(dw, red);
         const double a = rr / dw[0];
         double rn[1] = {0.0};
@@ -253,7 +260,10 @@ __host__ __device__ inline int64_t slot_bytes(int K, int64_t Mp, int64_t nIp) {
 // DL: the inner CG's search direction d lives in LDS (ldsd, M_j doubles)
 // instead of the workgroup's HBM slot, so the sparse product on S gathers it
 // from LDS and the CG's vector passes touch one vector fewer in HBM.
-template <int BD, int NT, bool SID, bool GAL, bool DL>
+// UNIT: S has exactly-identity diagonal blocks and the plan holds a copy of
+// its off-diagonal blocks alone (global system): the inner CG applies
+// S = I + (those blocks) and never reads the identity blocks.
+template <int BD, int NT, bool SID, bool GAL, bool DL, bool UNIT>
 __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L, double* ldsd) {
     const int tid = threadIdx.x;
     const int K = P.K;
@@ -269,7 +279,14 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L, doub
     const int M = sy.M;
     const int64_t Mp = P.Mp, nIp = P.nIp;
     const double* Hb = (const double*)P.Hv64;
-    const double* Sb = (const double*)P.Sv64;
+    const double* Sb = UNIT ? P.s_vals : (const double*)P.Sv64;
+    Sys syS = sy;
+    if constexpr (UNIT) {
+        syS.rowptr = P.s_rowptr;
+        syS.ecol = P.s_ecol;
+        syS.egid = nullptr;
+        syS.gbase = 0;
+    }
     const int nI = ri.nout;
     const int32_t* rows = P.out_local + ri.out_base;
 
@@ -298,7 +315,7 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L, doub
     }
     __syncthreads();
     double* q0 = SID ? t : q;
-    if constexpr (!SID) inner_total += inner_cg<BD, NT>(Sb, sy, t, q, res, d, wcg, 1.0, P.inner_tol, P.inner_maxiter,
+    if constexpr (!SID) inner_total += inner_cg<BD, NT, UNIT>(Sb, syS, t, q, res, d, wcg, 1.0, P.inner_tol, P.inner_maxiter,
                                                         L.red);
     __syncthreads();
     const double beta0 = sqrt(q0[ri.b_local]);
@@ -352,7 +369,7 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L, doub
         block_sum<NT, 1>(tt, L.red);
         // ---- q = S^{-1} t, beta_{n+1} = sqrt(q^T t)
         double* qq = SID ? t : q;
-        if constexpr (!SID) inner_total += inner_cg<BD, NT>(Sb, sy, t, q, res, d, wcg, tt[0], P.inner_tol,
+        if constexpr (!SID) inner_total += inner_cg<BD, NT, UNIT>(Sb, syS, t, q, res, d, wcg, tt[0], P.inner_tol,
                                                             P.inner_maxiter, L.red);
         double qt[1] = {0.0};
         if constexpr (SID) {
@@ -538,7 +555,7 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L, doub
     __syncthreads();
 }
 
-template <int BD, int NT, bool SID, bool GAL, bool DL>
+template <int BD, int NT, bool SID, bool GAL, bool DL, bool UNIT>
 __global__ __launch_bounds__(NT) void k_sqmr(KParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_job;
@@ -554,34 +571,38 @@ __global__ __launch_bounds__(NT) void k_sqmr(KParams P) {
         const int job = s_job;
         __syncthreads();
         if (job >= P.nrhs) break;
-        solve_one<BD, NT, SID, GAL, DL>(P, P.order[job], ws, L, ldsd);
+        solve_one<BD, NT, SID, GAL, DL, UNIT>(P, P.order[job], ws, L, ldsd);
     }
 }
 
+template <int BD, int NT, bool GAL>
+static void launch_dl(const KParams& P, bool unit, int slots, hipStream_t st) {
+    const size_t lds = lds_dir_offset(P.K, NT) + sizeof(double) * (size_t)P.Mp;
+    if (unit) hipLaunchKernelGGL((k_sqmr<BD, NT, false, GAL, true, true>), dim3(slots), dim3(NT), lds, st, P);
+    else hipLaunchKernelGGL((k_sqmr<BD, NT, false, GAL, true, false>), dim3(slots), dim3(NT), lds, st, P);
+}
+
 template <int BD, int NT>
-static hipError_t launch_nt(const KParams& P, bool sid, bool gal, bool dl, int slots, hipStream_t st) {
+static hipError_t launch_nt(const KParams& P, bool sid, bool gal, bool dl, bool unit, int slots, hipStream_t st) {
     const size_t lds = lds_bytes(P.K, NT);
     if (gal) {
-        if (sid) hipLaunchKernelGGL((k_sqmr<BD, NT, true, true, false>), dim3(slots), dim3(NT), lds, st, P);
-        else if (dl)
-            hipLaunchKernelGGL((k_sqmr<BD, NT, false, true, true>), dim3(slots), dim3(NT),
-                               lds_dir_offset(P.K, NT) + sizeof(double) * (size_t)P.Mp, st, P);
-        else hipLaunchKernelGGL((k_sqmr<BD, NT, false, true, false>), dim3(slots), dim3(NT), lds, st, P);
+        if (sid) hipLaunchKernelGGL((k_sqmr<BD, NT, true, true, false, false>), dim3(slots), dim3(NT), lds, st, P);
+        else if (dl) launch_dl<BD, NT, true>(P, unit, slots, st);
+        else hipLaunchKernelGGL((k_sqmr<BD, NT, false, true, false, false>), dim3(slots), dim3(NT), lds, st, P);
     } else {
-        if (sid) hipLaunchKernelGGL((k_sqmr<BD, NT, true, false, false>), dim3(slots), dim3(NT), lds, st, P);
-        else if (dl)
-            hipLaunchKernelGGL((k_sqmr<BD, NT, false, false, true>), dim3(slots), dim3(NT),
-                               lds_dir_offset(P.K, NT) + sizeof(double) * (size_t)P.Mp, st, P);
-        else hipLaunchKernelGGL((k_sqmr<BD, NT, false, false, false>), dim3(slots), dim3(NT), lds, st, P);
+        if (sid) hipLaunchKernelGGL((k_sqmr<BD, NT, true, false, false, false>), dim3(slots), dim3(NT), lds, st, P);
+        else if (dl) launch_dl<BD, NT, false>(P, unit, slots, st);
+        else hipLaunchKernelGGL((k_sqmr<BD, NT, false, false, false, false>), dim3(slots), dim3(NT), lds, st, P);
     }
     return hipGetLastError();
 }
 
 template <int BD>
-static hipError_t launch_bd(const KParams& P, bool sid, bool gal, bool dl, int nt, int slots, hipStream_t st) {
-    if (nt == 256) return launch_nt<BD, 256>(P, sid, gal, dl, slots, st);
-    if (nt == 1024) return launch_nt<BD, 1024>(P, sid, gal, dl, slots, st);
-    return launch_nt<BD, 512>(P, sid, gal, dl, slots, st);
+static hipError_t launch_bd(const KParams& P, bool sid, bool gal, bool dl, bool unit, int nt, int slots,
+                            hipStream_t st) {
+    if (nt == 256) return launch_nt<BD, 256>(P, sid, gal, dl, unit, slots, st);
+    if (nt == 1024) return launch_nt<BD, 1024>(P, sid, gal, dl, unit, slots, st);
+    return launch_nt<BD, 512>(P, sid, gal, dl, unit, slots, st);
 }
 
 }  // namespace qmr
@@ -592,12 +613,14 @@ size_t qmr_lds_bytes(int K, int nt, int64_t Mp, bool dl) {
 
 int64_t qmr_slot_bytes(int K, int64_t Mp, int64_t nIp) { return qmr::slot_bytes(K, Mp, nIp); }
 
-hipError_t launch_qmr(const KParams& P, int bd, bool sid, bool gal, bool dl, int nt, int slots, hipStream_t st) {
+hipError_t launch_qmr(const KParams& P, int bd, bool sid, bool gal, bool dl, bool unit, int nt, int slots,
+                      hipStream_t st) {
     if (dl && sid) return hipErrorInvalidValue;      // no inner CG when S = I
+    if (unit && (!dl || !P.s_rowptr || !P.s_ecol || !P.s_vals)) return hipErrorInvalidValue;
     switch (bd) {
-        case 1: return qmr::launch_bd<1>(P, sid, gal, dl, nt, slots, st);
-        case 4: return qmr::launch_bd<4>(P, sid, gal, dl, nt, slots, st);
-        case 9: return qmr::launch_bd<9>(P, sid, gal, dl, nt, slots, st);
+        case 1: return qmr::launch_bd<1>(P, sid, gal, dl, unit, nt, slots, st);
+        case 4: return qmr::launch_bd<4>(P, sid, gal, dl, unit, nt, slots, st);
+        case 9: return qmr::launch_bd<9>(P, sid, gal, dl, unit, nt, slots, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -122,6 +122,7 @@ struct scocg_plan {
     bool qmr = false;         // real S-Lanczos basis (QMR, or the COCG iterates if gal)
     bool gal = false;
     bool dl = false;          // Lanczos-COCG with the inner CG's direction in LDS
+    bool unit = false;        // S applied as I + a copy of its off-diagonal blocks (dsrow/dscol/dsval)
     int64_t nIp = 0;
     int64_t Mp = 0, slot_bytes = 0, out_count = 0;
     std::vector<int64_t> out_off;
@@ -135,6 +136,9 @@ struct scocg_plan {
     int32_t* doutl = nullptr;
     int64_t* doutoff = nullptr;
     double* dhout = nullptr;       // H_{row(o), j} of every output row o (scocg_plan_cohp)
+    int64_t* dsrow = nullptr;      // S's off-diagonal blocks alone (unit)
+    int32_t* dscol = nullptr;
+    double* dsval = nullptr;
     int32_t* dorder = nullptr;
     int32_t* dqueue = nullptr;
     char* dws = nullptr;
@@ -534,6 +538,9 @@ extern "C" void scocg_plan_free(scocg_plan* pl) {
     dev_free(pl->doutl);
     dev_free(pl->doutoff);
     dev_free(pl->dhout);
+    dev_free(pl->dsrow);
+    dev_free(pl->dscol);
+    dev_free(pl->dsval);
     dev_free(pl->dorder);
     dev_free(pl->dqueue);
     dev_free(pl->dws);
@@ -874,6 +881,33 @@ extern "C" scocg_status scocg_plan_create(scocg_problem* P, const scocg_options*
         output_h(P, nrhs, rhs_index, spec, hm, hout);
         if ((st = dev_upload(&pl->dhout, hout.data(), hout.size()))) return bail(st);
     }
+    if (pl->dl && pl->global && P->s_unit_diag) {
+        // S = I + its off-diagonal blocks: copy the nonzero off-diagonal blocks
+        // into their own CSR so that the inner CG never reads an identity block
+        const int bd = P->bd;
+        const size_t bb = (size_t)bd * bd;
+        std::vector<int64_t> srow((size_t)P->nb + 1, 0);
+        std::vector<int32_t> scol;
+        std::vector<double> sval;
+        for (int64_t a = 0; a < P->nb; ++a) {
+            for (int64_t e = P->rowptr[a]; e < P->rowptr[a + 1]; ++e) {
+                if (P->col[e] == a) continue;
+                const double* blk = P->hS.data() + (size_t)e * bb;
+                bool any = false;
+                for (size_t t = 0; t < bb && !any; ++t) any = blk[t] != 0.0;
+                if (!any) continue;
+                scol.push_back(P->col[e]);
+                sval.insert(sval.end(), blk, blk + bb);
+            }
+            srow[a + 1] = (int64_t)scol.size();
+        }
+        if ((st = dev_upload(&pl->dsrow, srow.data(), srow.size()))) return bail(st);
+        if (!scol.empty()) {
+            if ((st = dev_upload(&pl->dscol, scol.data(), scol.size()))) return bail(st);
+            if ((st = dev_upload(&pl->dsval, sval.data(), sval.size()))) return bail(st);
+            pl->unit = true;
+        }
+    }
     if ((st = dev_upload(&pl->dorder, order.data(), order.size()))) return bail(st);
     if (hipMalloc((void**)&pl->dqueue, sizeof(int32_t)) != hipSuccess) return bail(fail(SCOCG_E_NOMEM, "queue"));
     if (nrhs > 0) {
@@ -898,7 +932,7 @@ extern "C" scocg_status scocg_plan_info(const scocg_plan* pl, int64_t* info) {
     info[5] = (int64_t)(pl->qmr ? scocg::qmr_lds_bytes(pl->K, pl->nt, pl->Mp, pl->dl)
                                 : scocg::solver_lds_bytes(pl->K, pl->nt));
     info[6] = pl->prec;
-    info[7] = (pl->global ? 1 : 0) | (pl->proj ? 2 : 0) | (pl->qmr ? 4 : 0) | (pl->gal ? 8 : 0) | (pl->dl ? 16 : 0);
+    info[7] = (pl->global ? 1 : 0) | (pl->proj ? 2 : 0) | (pl->qmr ? 4 : 0) | (pl->gal ? 8 : 0) | (pl->dl ? 16 : 0) | (pl->unit ? 32 : 0);
     return SCOCG_OK;
 }
 
@@ -944,6 +978,9 @@ static KParams make_kparams(const scocg_plan* pl, scocg_z* out, int32_t* iters, 
     k.audit = pl->opt.audit;
     k.s_unit_diag = P->s_unit_diag ? 1 : 0;
     k.ent_direct = pl->global ? 1 : 0;     // the global system's egid is dIota
+    k.s_rowptr = pl->unit ? pl->dsrow : nullptr;
+    k.s_ecol = pl->unit ? pl->dscol : nullptr;
+    k.s_vals = pl->unit ? pl->dsval : nullptr;
     k.queue = pl->dqueue;
     k.ws = pl->dws;
     k.slot_bytes = pl->slot_bytes;
@@ -969,7 +1006,7 @@ extern "C" scocg_status scocg_plan_run(scocg_plan* pl, void* stream, scocg_z* ou
     KParams k = make_kparams(pl, out, iters, status, resid);
     (void)hipGetLastError();   // drop any error another caller left on this thread
     HIP_TRY(scocg::launch_fill_i32(pl->dqueue, 0, 1, st));
-    if (pl->qmr) HIP_TRY(scocg::launch_qmr(k, P->bd, !P->has_S, pl->gal, pl->dl, pl->nt, pl->slots, st));
+    if (pl->qmr) HIP_TRY(scocg::launch_qmr(k, P->bd, !P->has_S, pl->gal, pl->dl, pl->unit, pl->nt, pl->slots, st));
     else HIP_TRY(scocg::launch_solver(k, P->bd, pl->proj ? 3 : pl->prec, !P->has_S, pl->nt, pl->slots, st));
     return SCOCG_OK;
 }

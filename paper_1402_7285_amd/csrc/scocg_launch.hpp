@@ -20,7 +20,8 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 size_t qmr_lds_bytes(int K, int nt, int64_t Mp, bool dl);
 int64_t qmr_slot_bytes(int K, int64_t Mp, int64_t nIp);
 // gal: the COCG (Galerkin) iterates on the same basis instead of the QMR ones.
-hipError_t launch_qmr(const KParams& P, int bd, bool sid, bool gal, bool dl, int nt, int slots, hipStream_t st);
+hipError_t launch_qmr(const KParams& P, int bd, bool sid, bool gal, bool dl, bool unit, int nt, int slots,
+                      hipStream_t st);
 // Energy integration of a plan's output (integrate_kernels.hip).
 hipError_t launch_integrate(const double* G, const double* z, const double* w, const RhsInfo* rhs,
                             const int64_t* out_off, const int32_t* out_local, int nrhs, int K, double mu, double kT,

@@ -53,6 +53,11 @@ struct KParams {
     int32_t audit;             // FP32 forms
     int32_t s_unit_diag;       // S's diagonal blocks are exactly I
     int32_t ent_direct;        // egid is the identity: entry e holds block e
+    // S = I + off-diagonal blocks (global system, identity diagonal blocks):
+    // the off-diagonal blocks alone in their own CSR, entry e holding block e
+    const int64_t* s_rowptr;
+    const int32_t* s_ecol;
+    const double* s_vals;
     // work queue and per-workgroup memory
     int32_t* queue;            // next RHS to hand out
     char* ws;

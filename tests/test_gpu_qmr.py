@@ -52,6 +52,8 @@ def test_qmr_parity(B, case, threads):
     P, plan = _plan(B, prob, threads=threads)
     assert plan.info["global"] & 4
     assert bool(plan.info["global"] & 16) == (prob.S is not None)
+    # a global system whose S has identity diagonal blocks: S = I + off-diagonal copy
+    assert bool(plan.info["global"] & 32) == (prob.S is not None and prob.cluster_ptr is None)
     r = plan.solve()
     Hcsr = bsr_to_scipy(prob.H)
     Scsr = bsr_to_scipy(prob.S) if prob.S is not None else None
@@ -79,6 +81,7 @@ def test_cocg_on_lanczos_basis_parity(B, case, threads):
     assert plan.info["global"] & 8
     # with S != I the inner CG's direction is kept in LDS (it fits at these sizes)
     assert bool(plan.info["global"] & 16) == (prob.S is not None)
+    assert bool(plan.info["global"] & 32) == (prob.S is not None and prob.cluster_ptr is None)
     r = plan.solve()
     Hcsr = bsr_to_scipy(prob.H)
     Scsr = bsr_to_scipy(prob.S) if prob.S is not None else None
