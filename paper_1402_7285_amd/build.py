@@ -43,21 +43,24 @@ def build(verbose: bool = False) -> str:
     hipcc = _hipcc()
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    objs, cmds = [], []
     for src in sorted(os.listdir(CSRC)):
         path = os.path.join(CSRC, src)
         obj = os.path.join(objdir, src + ".o")
         if src.endswith(".hip"):
-            cmd = [hipcc, *HIP_FLAGS, "-c", path, "-o", obj]
+            cmds.append([hipcc, *HIP_FLAGS, "-c", path, "-o", obj])
         elif src.endswith(".cpp"):
             # host-only C++: plain g++ against the HIP runtime headers
-            cmd = [os.environ.get("CXX", "g++"), *HOST_FLAGS, "-c", path, "-o", obj]
+            cmds.append([os.environ.get("CXX", "g++"), *HOST_FLAGS, "-c", path, "-o", obj])
         else:
             continue
-        out = _run(cmd)
-        if verbose and out.strip():
-            print(out)
         objs.append(obj)
+    # the sources compile independently: one compiler process each, at once
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=max(1, min(len(cmds), os.cpu_count() or 1))) as ex:
+        for out in ex.map(_run, cmds):
+            if verbose and out.strip():
+                print(out)
     tmp = LIB + ".tmp"
     _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
     os.replace(tmp, LIB)
