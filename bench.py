@@ -327,7 +327,7 @@ def binning_ab(B, args):
 
     def timed(P, prob, kw, order=None):
         plan = B.Plan(P, prob.shifts, prob.rhs, tol=args.tol, threads=args.threads, slots=args.slots,
-                      order=order, **kw)
+                      order=order, method=METHODS[args.method], **kw)
         bufs = plan.alloc_outputs()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -384,7 +384,7 @@ def binning_ab(B, args):
            "gain_learned_vs_index": times["index"] / times["learned"],
            "gain_learned_vs_by_size": times["by_size"] / times["learned"],
            "pred_corr_log_iters": corr, "best_val_mse": best_val, "train_seconds": t_train,
-           "slots": plan0.info["slots"], "threads": plan0.info["threads"]}
+           "slots": plan0.info["slots"], "threads": plan0.info["threads"], "method": args.method}
     print(json.dumps(out), flush=True)
 
 
