@@ -39,6 +39,9 @@ CASES = {
     "fcc3_clusters": lambda: make_problem(name="fcc3-clusters", lattice="fcc", L=3, bdim=9, hop=(0.0, 0.5),
                                           s_scale=0.03, K=12, eta=0.05, nrhs=6, radius=(1.0, 1.6),
                                           seed_key=(6, 6, 6)),
+    # 9x9 blocks on a global system with S: direction in LDS, S as I plus its off-diagonal blocks
+    "fcc2_generalized": lambda: make_problem(name="fcc2-gen", lattice="fcc", L=2, bdim=9, hop=(0.0, 0.5),
+                                             s_scale=0.03, K=8, eta=0.05, nrhs=3, seed_key=(3, 9, 3)),
     # 4x4 blocks in cluster mode: the block index of each entry comes from its map
     "sc5_clusters": lambda: make_problem(name="sc5-clusters", lattice="sc", L=5, bdim=4, s_scale=0.03, K=8,
                                          eta=0.05, nrhs=4, radius=(1.0, 1.8), seed_key=(9, 2, 7)),
