@@ -22,11 +22,12 @@ import time
 
 import numpy as np
 
+T_START = time.perf_counter()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-METRIC = "converged (RHS×shift) solves/s at rel. res 1e-6: FP32+batched vs FP64 plain"
+METRIC = "converged (RHS×shift) solves/s at rel. res 1e-6 (FP64, batched persistent launch)"
 WORKLOADS = {
     "cfg1": dict(cfg=1, desc="generalized shifted COCG, simple-cubic 16^3, 4x4 blocks (M=16384), "
                              "S = I + N(0,0.03) blocks, 128 shifts E in [-8,8] + 0.02i, 256 RHS"),
@@ -187,10 +188,13 @@ def plain_baseline(B, P, prob, args, kw):
     print(json.dumps(out), flush=True)
 
 
-def measure_form(B, P, prob, kw, args, method, stream):
+def measure_form(B, P, prob, kw, args, method, stream, warmup, steps, warm_budget, time_budget):
     """Autotune (unless the launch shape is given), build the plan, run the
     warm-up and the timed steps of one form of the solve; returns the plan,
-    its buffers, the solves/s and the report fields (iterations, roofline)."""
+    its buffers, the solves/s and the report fields (iterations, roofline).
+    The warm-up stops after warm_budget seconds and the timed region holds
+    as many of `steps` whole solves as fit time_budget seconds (at least
+    one each); the counts actually run are returned."""
     import torch
     threads, slots, tuned = args.threads, args.slots, None
     if not args.no_autotune and not args.threads and not args.slots:
@@ -207,27 +211,50 @@ def measure_form(B, P, prob, kw, args, method, stream):
     qmr = bool(plan.info["global"] & 4)
     gal = bool(plan.info["global"] & 8)
     bufs = plan.alloc_outputs()
-    for w in range(args.warmup):
+    # warm-up: up to `warmup` steps, stopping once they have used warm_budget seconds (at least one step
+    # when warmup >= 1); the first one also gives the step time that sizes the timed region
+    warm_done, t_warm, step_est = 0, 0.0, None
+    for w in range(warmup):
+        t1 = time.perf_counter()
         plan.run(bufs, stream)
         torch.cuda.synchronize()
-        print(f"[bench] {method}: warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        dt = time.perf_counter() - t1
+        step_est = dt if step_est is None else min(step_est, dt)
+        t_warm += dt
+        warm_done += 1
+        print(f"[bench] {method}: warmup {w + 1}/{warmup} done ({dt:.2f} s)", file=sys.stderr, flush=True)
+        if t_warm + step_est > warm_budget:
+            break
+    # timed steps: as many of the requested `steps` as fit time_budget seconds (at least one)
+    n_steps = steps
+    if step_est is not None and time_budget > 0:
+        n_steps = max(1, min(steps, int(time_budget // max(step_est, 1e-6))))
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(n_steps):
         ev[i][0].record(stream)
         plan.run(bufs, stream)
         ev[i][1].record(stream)
         torch.cuda.synchronize()
-        print(f"[bench] {method}: step {i + 1}/{args.steps}: {ev[i][0].elapsed_time(ev[i][1]) / 1e3:.2f} s",
+        print(f"[bench] {method}: step {i + 1}/{n_steps}: {ev[i][0].elapsed_time(ev[i][1]) / 1e3:.2f} s",
               file=sys.stderr, flush=True)
+        if step_est is None and time_budget > 0:
+            # no warm-up: size the timed region from the first step
+            step_est = ev[0][0].elapsed_time(ev[0][1]) / 1e3
+            n_steps_fit = max(1, min(steps, int(time_budget // max(step_est, 1e-6))))
+            if n_steps_fit < n_steps:
+                ev = ev[:n_steps_fit]
+                n_steps = n_steps_fit
+        if i + 1 >= n_steps:
+            break
     wall = time.perf_counter() - t0
     kernel_s = float(np.mean([a.elapsed_time(b) for a, b in ev])) / 1e3
     status = bufs["status"].cpu().numpy()
     resid = bufs["resid"].cpu().numpy()
     good = int(np.sum((status == 0) & (resid <= 1e-6)))
     stats = plan.stats()
-    ms_per_step = wall / args.steps * 1e3
+    ms_per_step = wall / n_steps * 1e3
     nout = np.diff(prob.out_ptr)
     w_share = min(plan.info["slots"], prob.nrhs) if prob.cluster_ptr is None else 1
     if qmr:
@@ -252,7 +279,8 @@ def measure_form(B, P, prob, kw, args, method, stream):
             "seed-switching COCG, projected rows (three-term seed)" if projected else "seed-switching COCG, full x")
     cpu_form = "lanczos" if gal else "qmr" if qmr else projected
     return dict(plan=plan, bufs=bufs, value=good / (ms_per_step / 1e3), ms_per_step=ms_per_step, stats=stats,
-                report=report, form=form, cpu_form=cpu_form, autotuned=tuned is not None)
+                report=report, form=form, cpu_form=cpu_form, autotuned=tuned is not None, steps=n_steps,
+                warmup=warm_done, wall_s=wall, step_s=kernel_s)
 
 
 def chunked(B, P, prob, kw, args):
@@ -428,8 +456,17 @@ def measured_traffic(args, form, alg_bytes):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--time-budget", type=float, default=75.0,
+                    help="seconds for the timed steps: as many of --steps whole solves as fit (at least one)")
+    ap.add_argument("--warm-budget", type=float, default=30.0,
+                    help="seconds for the warm-up: up to --warmup solves, at least one if --warmup >= 1")
+    ap.add_argument("--deadline", type=float, default=480.0,
+                    help="wall seconds from start after which the optional legs (seed-switching companion, "
+                         "CPU baseline) are skipped")
+    ap.add_argument("--companion-ratio", type=float, default=3.0,
+                    help="expected solve time of the seed-switching form relative to the headline form")
     ap.add_argument("--workload", default="cfg1", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=sorted(PREC))
     ap.add_argument("--nrhs", type=int, default=0, help="0 = the workload's full RHS set")
@@ -487,27 +524,38 @@ def main():
     if args.chunk:
         return chunked(B, P, prob, kw, args)
     stream = torch.cuda.current_stream()
-    r = measure_form(B, P, prob, kw, args, args.method, stream)
+    r = measure_form(B, P, prob, kw, args, args.method, stream, args.warmup, args.steps, args.warm_budget,
+                     args.time_budget)
     plan, bufs = r["plan"], r["bufs"]
     out = {
-        "metric": METRIC, "value": r["value"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": r["value"], "unit": "solves/s", "n_gpus": 1, "steps": r["steps"],
+        "warmup": r["warmup"], "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": {"fp64": "c128", "fp32": "c64", "bf16": "c64/bf16"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {wl['desc']}", "nrhs": prob.nrhs, "shifts": prob.nshift,
                    "M": prob.M, "tol": args.tol, "precision": args.precision, "batched": "persistent",
                    "slots": plan.info["slots"], "threads": plan.info["threads"], "form": r["form"],
                    "lds_bytes": plan.info["lds_bytes"], "cg_direction_in_lds": bool(plan.info["global"] & 16),
-                   "autotuned": r["autotuned"]},
+                   "autotuned": r["autotuned"], "steps_requested": args.steps, "warmup_requested": args.warmup,
+                   "time_budget_s": args.time_budget},
         **r["report"],
     }
+    print(f"[bench] headline: {r['value']:.1f} solves/s over {r['steps']} timed steps "
+          f"({r['ms_per_step'] / 1e3:.2f} s each)", file=sys.stderr, flush=True)
+    left = args.deadline - (time.perf_counter() - T_START)
     if args.method != "cocg" and not args.no_companion:
-        # the seed-switching form of the same method, timed in the same run
-        c = measure_form(B, P, prob, kw, args, "cocg", stream)
-        out["seed_switching_form"] = {"form": c["form"], "value": c["value"], "ms_per_step": c["ms_per_step"],
-                                      "threads": c["plan"].info["threads"], "slots": c["plan"].info["slots"],
-                                      **c["report"]}
-        del c
+        # the seed-switching form of the same method, timed in the same run (one step, no warm-up beyond
+        # the autotuner's probes), only if the time left allows it: its solve takes about
+        # companion_ratio times the headline form's
+        est = r["step_s"] * args.companion_ratio
+        if left > 2.0 * est + 60.0:
+            c = measure_form(B, P, prob, kw, args, "cocg", stream, 0, 1, 0.0, 0.0)
+            out["seed_switching_form"] = {"form": c["form"], "value": c["value"], "ms_per_step": c["ms_per_step"],
+                                          "steps": c["steps"], "threads": c["plan"].info["threads"],
+                                          "slots": c["plan"].info["slots"], **c["report"]}
+            del c
+        else:
+            out["seed_switching_form"] = {"skipped": f"estimated {est:.0f} s, {left:.0f} s left before the deadline"}
     w = np.zeros(prob.nshift)
     if prob.nshift > 1:
         dE = np.diff(prob.shifts.real)
@@ -527,8 +575,15 @@ def main():
                                          "mu = 0, kT = 0.1)"}
     if not args.no_cpu_baseline:
         workers = max(1, min(16, os.cpu_count() or 1))
-        print(f"[bench] cpu baseline: oracle on {workers} processes ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(prob, r["stats"], args.cpu_rhs, args.cpu_iters, workers, r["cpu_form"])
+        left = args.deadline - (time.perf_counter() - T_START)
+        if left > 90.0:
+            print(f"[bench] cpu baseline: oracle on {workers} processes ...", file=sys.stderr, flush=True)
+            out["cpu_baseline"] = cpu_baseline(prob, r["stats"], args.cpu_rhs, args.cpu_iters, workers,
+                                               r["cpu_form"])
+        else:
+            out["cpu_baseline"] = None
+            print(f"[bench] cpu baseline skipped: {left:.0f} s left before the deadline", file=sys.stderr,
+                  flush=True)
     print(json.dumps(out), flush=True)
 
 
