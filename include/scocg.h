@@ -55,6 +55,9 @@ typedef int32_t scocg_status;
 #define SCOCG_MAXITER    1   /* iteration limit reached; partial x returned */
 #define SCOCG_BREAKDOWN  2   /* zero pivot (mu = 0, pi = 0 or gamma = 0) */
 #define SCOCG_NONFINITE  3   /* NaN / Inf met in the recurrences */
+#define SCOCG_ABORTED    4   /* team solver: a wait between the workgroups of a team
+                                exceeded its bound and the run was abandoned (the
+                                plan's stats call then fails with E_DEVICE) */
 
 /* ---- precision of the vectors and stored blocks --------------------------- */
 #define SCOCG_FP64        0  /* complex128 vectors, FP64 blocks */
@@ -185,11 +188,21 @@ typedef struct {
                                shift's tridiagonal, with no seed; resid is the
                                residual norm |zeta_n| ||t|| the recurrences give.
                                Same restrictions as QMR. */
+    int32_t team_size;      /* the two real Lanczos-basis methods: workgroups that solve
+                               one panel of right-hand sides together, splitting its
+                               rows (1..32); 0 = chosen by the library; -1 = one
+                               workgroup per right-hand side (the one-workgroup
+                               solver).  Other methods ignore it. */
+    int32_t panel_width;    /* right-hand sides solved together by one team, sharing
+                               every block read of H and S: 1, 4 or 8 (4 and 8 need
+                               4x4 blocks and every RHS on the whole system; with 4x4
+                               blocks the block products then run on FP64 matrix
+                               cores); 0 = chosen by the library. */
 } scocg_options;
 
 /* Defaults: tol 1e-10, maxiter 0, FP64, replace_every 0, inner_maxiter 1000,
  * inner_tol 1e-13, inner_tol_lo 1e-6, seed_index -1, threads 0, slots 0, audit 1,
- * projected 1, method COCG. */
+ * projected 1, method COCG, team_size 0, panel_width 0. */
 void scocg_options_default(scocg_options* opt);
 
 /* ---- right-hand sides ----------------------------------------------------- */
@@ -250,9 +263,12 @@ int64_t scocg_plan_out_count(const scocg_plan* plan);
  * method with S != I, when M_j doubles fit beside the per-shift arrays);
  * bit 5: with bit 4 on a global system whose S has exactly-identity
  * diagonal blocks, S is applied as I plus a plan-held copy of its nonzero
- * off-diagonal blocks.
+ * off-diagonal blocks; bit 6: the team solver runs (then [0] is the number of
+ * workgroups of all teams and [3] the bytes of one team's working memory);
+ * bit 7: its block products run on FP64 matrix cores.  [8] workgroups per
+ * team (1 for the other solvers), [9] panel width (right-hand sides per team).
  */
-#define SCOCG_NINFO 8
+#define SCOCG_NINFO 10
 scocg_status scocg_plan_info(const scocg_plan* plan, int64_t* info);
 
 /* out_offset(r) for every RHS (host int64[nrhs+1], prefix sums of n_out). */
@@ -283,18 +299,33 @@ scocg_status scocg_plan_capture(scocg_plan* plan, void* stream, scocg_z* out, in
 scocg_status scocg_plan_replay(scocg_plan* plan, void* stream);
 
 /*
- * Autotuner: times one probe solve (every RHS capped at probe_iters outer
- * iterations, after a warm-up) for each workgroup size in {256, 512, 1024}
- * and each count of resident workgroups per compute unit in {1, 2}, and
- * returns the fastest pair (threads, total resident workgroups) and its
- * probe time in seconds.  The arguments are those of scocg_plan_create; the
- * caller caches the answer (the Python binding keys a JSON file by GPU
- * architecture and problem shape).
+ * Autotuner of the one-workgroup solvers: times one probe solve (every RHS
+ * capped at probe_iters outer iterations, after a warm-up) for each
+ * workgroup size in {256, 512, 1024} and each count of resident workgroups
+ * per compute unit in {1, 2} (team_size -1), and returns the fastest pair
+ * (threads, total resident workgroups) and its probe time in seconds.  The
+ * arguments are those of scocg_plan_create; the caller caches the answer
+ * (the Python binding keys a JSON file by GPU architecture and problem
+ * shape).  The team solver's shape is searched by scocg_autotune_team.
  */
 scocg_status scocg_autotune(scocg_problem* P, const scocg_options* opt, int32_t nshift,
                             const scocg_z* shifts, int32_t nrhs, const int32_t* rhs_index,
                             const scocg_rhs_spec* spec, int32_t probe_iters, int32_t* best_threads,
                             int32_t* best_slots, double* best_seconds);
+
+/*
+ * Autotuner of the team solver (the two real Lanczos-basis methods): times
+ * one probe solve (every RHS capped at probe_iters outer iterations, after a
+ * warm-up) for each candidate launch - panel width, workgroups per team and
+ * workgroup size, and the one-workgroup solver - and writes the fastest into
+ * *best: a copy of *opt with threads, slots, team_size and panel_width set
+ * (maxiter as in *opt).  Candidates that do not fit the device are skipped;
+ * E_UNSUPPORTED if none fits, E_ARG for another method.
+ */
+scocg_status scocg_autotune_team(scocg_problem* P, const scocg_options* opt, int32_t nshift,
+                                 const scocg_z* shifts, int32_t nrhs, const int32_t* rhs_index,
+                                 const scocg_rhs_spec* spec, int32_t probe_iters, scocg_options* best,
+                                 double* best_seconds);
 
 /* ---- learned RHS-cost predictor (for the work-queue order) ----------------- */
 /*

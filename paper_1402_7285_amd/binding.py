@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libscocg.so")
 # return codes (include/scocg.h)
 OK, W_PARTIAL, W_S_DIAG = 0, 1, 2
 E_ARG, E_SHAPE, E_NOT_SYMMETRIC, E_DEVICE, E_NOMEM, E_UNSUPPORTED = -1, -2, -3, -4, -5, -6
-CONVERGED, MAXITER, BREAKDOWN, NONFINITE = 0, 1, 2, 3
+CONVERGED, MAXITER, BREAKDOWN, NONFINITE, ABORTED = 0, 1, 2, 3, 4
 FP64, FP32, FP32_BF16 = 0, 1, 2
 OUT_SELECTED_G, OUT_FULL_X = 0, 1
 METHOD_COCG, METHOD_QMR, METHOD_COCG_LANCZOS = 0, 1, 2
@@ -34,7 +34,7 @@ EXPORTS = (
     "scocg_autotune", "scocg_features", "scocg_mlp_nparams", "scocg_mlp_work_floats", "scocg_mlp_forward",
     "scocg_mlp_train_step", "scocg_plan_integrate", "scocg_matrix_from_mtx", "scocg_matrix_shape",
     "scocg_matrix_export_bsr", "scocg_solve_device", "scocg_sync", "scocg_mlp_cfg_default",
-    "scocg_mlp_model_floats", "scocg_mlp_train", "scocg_mlp_predict", "scocg_plan_cohp",
+    "scocg_mlp_model_floats", "scocg_mlp_train", "scocg_mlp_predict", "scocg_plan_cohp", "scocg_autotune_team",
 )
 
 
@@ -52,7 +52,8 @@ class scocg_options(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int32), ("precision", C.c_int32),
                 ("replace_every", C.c_int32), ("inner_maxiter", C.c_int32), ("inner_tol", C.c_double),
                 ("inner_tol_lo", C.c_double), ("seed_index", C.c_int32), ("threads", C.c_int32),
-                ("slots", C.c_int32), ("audit", C.c_int32), ("projected", C.c_int32), ("method", C.c_int32)]
+                ("slots", C.c_int32), ("audit", C.c_int32), ("projected", C.c_int32), ("method", C.c_int32),
+                ("team_size", C.c_int32), ("panel_width", C.c_int32)]
 
 
 class scocg_rhs_spec(C.Structure):
@@ -102,6 +103,8 @@ def _declare(lib):
         "scocg_mlp_train_step": (st, [_VP, _VP, _VP, _VP, _VP, _VP, i64, C.c_float, i32, _VP, _VP, _VP, _VP]),
         "scocg_autotune": (st, [_VP, C.POINTER(scocg_options), i32, _VP, i32, _VP, C.POINTER(scocg_rhs_spec),
                                 i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_double)]),
+        "scocg_autotune_team": (st, [_VP, C.POINTER(scocg_options), i32, _VP, i32, _VP, C.POINTER(scocg_rhs_spec),
+                                     i32, C.POINTER(scocg_options), C.POINTER(C.c_double)]),
         "scocg_solve": (st, [_VP, C.POINTER(scocg_options), i32, _VP, i32, _VP,
                              C.POINTER(scocg_rhs_spec), _VP, _VP, _VP, _VP]),
         "scocg_solve_device": (st, [_VP, C.POINTER(scocg_options), i32, _VP, i32, _VP,
@@ -236,8 +239,9 @@ def scocg_plan_out_offsets(h, nrhs) -> np.ndarray:
     return off
 
 
-NINFO = 8
-INFO_NAMES = ("slots", "threads", "Mp", "slot_bytes", "seed0", "lds_bytes", "precision", "global")
+NINFO = 10
+INFO_NAMES = ("slots", "threads", "Mp", "slot_bytes", "seed0", "lds_bytes", "precision", "global", "team_size",
+              "panel_width")
 
 
 def scocg_plan_info(h) -> dict:
@@ -268,6 +272,17 @@ def scocg_autotune(problem, opt, shifts, rhs_index, spec: "_Spec", probe_iters):
     _check(load().scocg_autotune(problem, C.byref(opt), int(z.size), zp, int(rhs.size), _ptr(rhs),
                                  C.byref(spec.struct), int(probe_iters), C.byref(t), C.byref(sl), C.byref(sec)))
     return int(t.value), int(sl.value), float(sec.value)
+
+
+def scocg_autotune_team(problem, opt, shifts, rhs_index, spec: "_Spec", probe_iters):
+    """Team-solver launch search; returns (best options struct, probe seconds)."""
+    z, zp = _shifts(shifts)
+    rhs = np.ascontiguousarray(rhs_index, dtype=np.int32)
+    best = scocg_options()
+    sec = C.c_double(0.0)
+    _check(load().scocg_autotune_team(problem, C.byref(opt), int(z.size), zp, int(rhs.size), _ptr(rhs),
+                                      C.byref(spec.struct), int(probe_iters), C.byref(best), C.byref(sec)))
+    return best, float(sec.value)
 
 
 def _sp(stream):
@@ -542,9 +557,12 @@ class Plan:
 
 
 def autotune(problem: Problem, shifts, rhs, probe_iters=200, cache_path=None, key_extra="", **plan_kwargs):
-    """Pick (threads, slots) for this problem shape by timing short probe solves
-    on the device; results are cached in a JSON file keyed by the GPU
-    architecture and the problem shape."""
+    """Pick the launch shape for this problem by timing short probe solves on
+    the device: (threads, slots) of the one-workgroup solvers, or, for the
+    Lanczos-basis methods, (threads, slots, team_size, panel_width) of the
+    team solver (which includes the one-workgroup shape as team_size -1).
+    Results are cached in a JSON file keyed by the GPU architecture and the
+    problem shape."""
     import json
     import torch
     opts = {k: v for k, v in plan_kwargs.items() if hasattr(scocg_options, k)}
@@ -561,8 +579,13 @@ def autotune(problem: Problem, shifts, rhs, probe_iters=200, cache_path=None, ke
             return cache[key]
     opt = scocg_options_default(**opts)
     spec = make_spec(**spec_kw)
-    t, sl, sec = scocg_autotune(problem.h, opt, shifts, rhs, spec, probe_iters)
-    res = {"threads": t, "slots": sl, "probe_seconds": sec, "probe_iters": probe_iters}
+    if opt.method in (METHOD_QMR, METHOD_COCG_LANCZOS) and opt.team_size != -1:
+        best, sec = scocg_autotune_team(problem.h, opt, shifts, rhs, spec, probe_iters)
+        res = {"threads": int(best.threads), "slots": int(best.slots), "team_size": int(best.team_size),
+               "panel_width": int(best.panel_width), "probe_seconds": sec, "probe_iters": probe_iters}
+    else:
+        t, sl, sec = scocg_autotune(problem.h, opt, shifts, rhs, spec, probe_iters)
+        res = {"threads": t, "slots": sl, "probe_seconds": sec, "probe_iters": probe_iters}
     if cache_path:
         cache[key] = res
         with open(cache_path, "w") as f:

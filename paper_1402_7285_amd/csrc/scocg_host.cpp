@@ -123,6 +123,14 @@ struct scocg_plan {
     bool gal = false;
     bool dl = false;          // Lanczos-COCG with the inner CG's direction in LDS
     bool unit = false;        // S applied as I + a copy of its off-diagonal blocks (dsrow/dscol/dsval)
+    // team (panel) solver of the Lanczos-basis methods
+    bool team = false;
+    int G = 1, W = 1, nteams = 0, variant = 0, pairs_max = 0, rows_max = 0, pstride = 0;
+    bool team_dl = false;
+    size_t team_lds = 0;
+    int64_t spin_ticks = 0;
+    int32_t* dctl = nullptr;       // [0] queue, [1] abort flag, [32 ..) 32 ints per team
+    double* dpart = nullptr;       // teams' reduction partials
     int64_t nIp = 0;
     int64_t Mp = 0, slot_bytes = 0, out_count = 0;
     std::vector<int64_t> out_off;
@@ -499,6 +507,8 @@ extern "C" void scocg_options_default(scocg_options* o) {
     o->audit = 1;
     o->projected = 1;
     o->method = SCOCG_METHOD_COCG;
+    o->team_size = 0;
+    o->panel_width = 0;
 }
 
 // Initial seed: smallest |Im z|, then Re z closest to the median of Re z
@@ -545,6 +555,8 @@ extern "C" void scocg_plan_free(scocg_plan* pl) {
     dev_free(pl->dqueue);
     dev_free(pl->dws);
     dev_free(pl->dstats);
+    dev_free(pl->dctl);
+    dev_free(pl->dpart);
     delete pl;
 }
 
@@ -855,6 +867,95 @@ extern "C" scocg_status scocg_plan_create(scocg_problem* P, const scocg_options*
     }
     pl->slots = slots;
 
+    // S = I + its off-diagonal blocks (Lanczos-basis forms on a global system whose diagonal blocks of S
+    // are exactly I): a copy of the nonzero off-diagonal blocks in their own CSR, so that the inner CG
+    // never reads an identity block
+    std::vector<int64_t> srow_h;
+    std::vector<int32_t> scol_h;
+    std::vector<double> sval_h;
+    if (pl->qmr && P->has_S && pl->global && P->s_unit_diag) {
+        const int bd = P->bd;
+        const size_t bb = (size_t)bd * bd;
+        srow_h.assign((size_t)P->nb + 1, 0);
+        for (int64_t a = 0; a < P->nb; ++a) {
+            for (int64_t e = P->rowptr[a]; e < P->rowptr[a + 1]; ++e) {
+                if (P->col[e] == a) continue;
+                const double* blk = P->hS.data() + (size_t)e * bb;
+                bool any = false;
+                for (size_t t = 0; t < bb && !any; ++t) any = blk[t] != 0.0;
+                if (!any) continue;
+                scol_h.push_back(P->col[e]);
+                sval_h.insert(sval_h.end(), blk, blk + bb);
+            }
+            srow_h[a + 1] = (int64_t)scol_h.size();
+        }
+        if (scol_h.empty()) srow_h.clear();
+        else pl->unit = true;
+    }
+
+    // ---- team (panel) solver of the Lanczos-basis methods
+    if (pl->qmr && opt.team_size >= 0 && nrhs > 0) {
+        int W = opt.panel_width, G = opt.team_size;
+        const bool can_panel = pl->global && P->bd == 4;
+        if (W != 0 && W != 1 && W != 4 && W != 8) return bail(fail(SCOCG_E_ARG, "panel_width must be 0, 1, 4 or 8"));
+        if (W > 1 && !can_panel)
+            return bail(fail(SCOCG_E_UNSUPPORTED, "panels of several RHS need 4x4 blocks and the whole system"));
+        if (G > 32) return bail(fail(SCOCG_E_ARG, "team_size must be -1 .. 32"));
+        if (W == 0) W = can_panel ? (nrhs >= 64 ? 8 : (nrhs >= 16 ? 4 : 1)) : 1;
+        const int npanels = (nrhs + W - 1) / W;
+        if (G == 0) {
+            if (pl->global) {
+                // enough teams to fill the compute units, at least 64 block rows per workgroup
+                G = 1;
+                while (G < 8 && (int64_t)npanels * G * 2 <= cus && P->nb >= (int64_t)G * 2 * 64) G *= 2;
+            } else {
+                G = hm.maxM >= 6144 ? 8 : (hm.maxM >= 3072 ? 4 : (hm.maxM >= 1536 ? 2 : 1));
+            }
+        }
+        if (G > 1 || W > 1) {
+            if (opt.threads != 0 && opt.threads != 512 && opt.threads != 1024)
+                return bail(fail(SCOCG_E_ARG, "the team solver runs 512 or 1024 threads per workgroup"));
+            pl->team = true;
+            pl->G = G;
+            pl->W = W;
+            pl->nt = opt.threads ? opt.threads : (W >= 8 ? 1024 : 512);
+            pl->pairs_max = (W * nshift + G - 1) / G;
+            int64_t maxshare = 0;
+            for (const auto& sy : hm.sys) maxshare = std::max<int64_t>(maxshare, ((int64_t)sy.nrows + G - 1) / G);
+            pl->rows_max = (int)(maxshare * P->bd);
+            // 160 KB of LDS per workgroup, less the kernel's own few static words
+            const size_t lds_cap = 160 * 1024 - 256;
+            pl->team_dl = P->has_S && scocg::team_lds_bytes(pl->nt, W, pl->pairs_max, pl->rows_max, true) <= lds_cap;
+            pl->team_lds = scocg::team_lds_bytes(pl->nt, W, pl->pairs_max, pl->rows_max, pl->team_dl);
+            if (pl->team_lds > lds_cap) return bail(fail(SCOCG_E_UNSUPPORTED, "too many shifts for LDS"));
+            pl->variant = !P->has_S ? 0 : (pl->team_dl ? (pl->unit ? 2 : 1) : 3);
+            int per_cu = 0;
+            if (scocg::team_occupancy(P->bd, pl->gal, pl->variant, pl->nt, W, pl->team_lds, &per_cu) != hipSuccess ||
+                per_cu < 1)
+                return bail(fail(SCOCG_E_UNSUPPORTED, "team kernel does not fit a compute unit"));
+            const int maxwg = cus * per_cu;
+            if (G > maxwg) return bail(fail(SCOCG_E_UNSUPPORTED, "team larger than the resident workgroups"));
+            int nteams = std::min(npanels, maxwg / G);
+            if (opt.slots) nteams = std::min(nteams, std::max(1, opt.slots / G));
+            if (nteams >= 8) nteams -= nteams % 8;   // whole teams on every XCD
+            pl->slot_bytes = scocg::team_ws_bytes(W, nshift, pl->Mp, pl->nIp, !pl->gal);
+            if (hipMemGetInfo(&freeb, &totb) == hipSuccess && freeb > 0) {
+                const int64_t cap = (int64_t)(0.8 * (double)freeb) / std::max<int64_t>(1, pl->slot_bytes);
+                if (cap < 1) return bail(fail(SCOCG_E_NOMEM, "one team's memory (%lld bytes) exceeds free memory",
+                                              (long long)pl->slot_bytes));
+                nteams = (int)std::min<int64_t>(nteams, cap);
+            }
+            pl->nteams = nteams;
+            pl->slots = nteams * G;
+            pl->pstride = (2 * W + 15) / 16 * 16;
+            int rate_khz = 0;
+            if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, P->device) != hipSuccess ||
+                rate_khz <= 0)
+                rate_khz = 100000;
+            pl->spin_ticks = (int64_t)rate_khz * 1000 * 5;     // a wait is abandoned after 5 s
+        }
+    }
+
     std::vector<double> zz(2 * nshift);
     for (int k = 0; k < nshift; ++k) {
         zz[2 * k] = shifts[k].re;
@@ -881,38 +982,22 @@ extern "C" scocg_status scocg_plan_create(scocg_problem* P, const scocg_options*
         output_h(P, nrhs, rhs_index, spec, hm, hout);
         if ((st = dev_upload(&pl->dhout, hout.data(), hout.size()))) return bail(st);
     }
-    if (pl->dl && pl->global && P->s_unit_diag) {
-        // S = I + its off-diagonal blocks: copy the nonzero off-diagonal blocks
-        // into their own CSR so that the inner CG never reads an identity block
-        const int bd = P->bd;
-        const size_t bb = (size_t)bd * bd;
-        std::vector<int64_t> srow((size_t)P->nb + 1, 0);
-        std::vector<int32_t> scol;
-        std::vector<double> sval;
-        for (int64_t a = 0; a < P->nb; ++a) {
-            for (int64_t e = P->rowptr[a]; e < P->rowptr[a + 1]; ++e) {
-                if (P->col[e] == a) continue;
-                const double* blk = P->hS.data() + (size_t)e * bb;
-                bool any = false;
-                for (size_t t = 0; t < bb && !any; ++t) any = blk[t] != 0.0;
-                if (!any) continue;
-                scol.push_back(P->col[e]);
-                sval.insert(sval.end(), blk, blk + bb);
-            }
-            srow[a + 1] = (int64_t)scol.size();
-        }
-        if ((st = dev_upload(&pl->dsrow, srow.data(), srow.size()))) return bail(st);
-        if (!scol.empty()) {
-            if ((st = dev_upload(&pl->dscol, scol.data(), scol.size()))) return bail(st);
-            if ((st = dev_upload(&pl->dsval, sval.data(), sval.size()))) return bail(st);
-            pl->unit = true;
-        }
+    if (!srow_h.empty()) {
+        if ((st = dev_upload(&pl->dsrow, srow_h.data(), srow_h.size()))) return bail(st);
+        if ((st = dev_upload(&pl->dscol, scol_h.data(), scol_h.size()))) return bail(st);
+        if ((st = dev_upload(&pl->dsval, sval_h.data(), sval_h.size()))) return bail(st);
     }
     if ((st = dev_upload(&pl->dorder, order.data(), order.size()))) return bail(st);
     if (hipMalloc((void**)&pl->dqueue, sizeof(int32_t)) != hipSuccess) return bail(fail(SCOCG_E_NOMEM, "queue"));
+    if (pl->team) {
+        if (hipMalloc((void**)&pl->dctl, sizeof(int32_t) * 32 * (size_t)(pl->nteams + 1)) != hipSuccess ||
+            hipMalloc((void**)&pl->dpart, sizeof(double) * 2 * (size_t)pl->G * pl->pstride * pl->nteams) != hipSuccess)
+            return bail(fail(SCOCG_E_NOMEM, "team synchronisation buffers"));
+    }
     if (nrhs > 0) {
-        if (hipMalloc((void**)&pl->dws, (size_t)pl->slot_bytes * slots) != hipSuccess)
-            return bail(fail(SCOCG_E_NOMEM, "workspace of %lld bytes", (long long)pl->slot_bytes * slots));
+        const int64_t units = pl->team ? pl->nteams : pl->slots;
+        if (hipMalloc((void**)&pl->dws, (size_t)pl->slot_bytes * units) != hipSuccess)
+            return bail(fail(SCOCG_E_NOMEM, "workspace of %lld bytes", (long long)pl->slot_bytes * units));
         if (hipMalloc((void**)&pl->dstats, sizeof(int64_t) * scocg::NSTAT * nrhs) != hipSuccess)
             return bail(fail(SCOCG_E_NOMEM, "stats"));
     }
@@ -932,7 +1017,14 @@ extern "C" scocg_status scocg_plan_info(const scocg_plan* pl, int64_t* info) {
     info[5] = (int64_t)(pl->qmr ? scocg::qmr_lds_bytes(pl->K, pl->nt, pl->Mp, pl->dl)
                                 : scocg::solver_lds_bytes(pl->K, pl->nt));
     info[6] = pl->prec;
-    info[7] = (pl->global ? 1 : 0) | (pl->proj ? 2 : 0) | (pl->qmr ? 4 : 0) | (pl->gal ? 8 : 0) | (pl->dl ? 16 : 0) | (pl->unit ? 32 : 0);
+    const bool dl = pl->team ? pl->team_dl : pl->dl;
+    const bool unit = pl->team ? pl->variant == 2 : (pl->unit && pl->dl);
+    const bool mfma = pl->team && pl->P->bd == 4 && pl->W % 4 == 0;
+    info[7] = (pl->global ? 1 : 0) | (pl->proj ? 2 : 0) | (pl->qmr ? 4 : 0) | (pl->gal ? 8 : 0) | (dl ? 16 : 0) |
+              (unit ? 32 : 0) | (pl->team ? 64 : 0) | (mfma ? 128 : 0);
+    if (pl->team) info[5] = (int64_t)pl->team_lds;
+    info[8] = pl->team ? pl->G : 1;
+    info[9] = pl->team ? pl->W : 1;
     return SCOCG_OK;
 }
 
@@ -1005,8 +1097,34 @@ extern "C" scocg_status scocg_plan_run(scocg_plan* pl, void* stream, scocg_z* ou
     const scocg_problem* P = pl->P;
     KParams k = make_kparams(pl, out, iters, status, resid);
     (void)hipGetLastError();   // drop any error another caller left on this thread
+    if (pl->team) {
+        // queue, abort flag and every team's counters start at zero; the per-RHS counters too (the
+        // teams add their shift updates into them)
+        HIP_TRY(scocg::launch_fill_i32(pl->dctl, 0, 32 * (int64_t)(pl->nteams + 1), st));
+        HIP_TRY(scocg::launch_fill_i32((int32_t*)pl->dstats, 0, 2 * (int64_t)scocg::NSTAT * pl->nrhs, st));
+        scocg::TParams T{};
+        T.k = k;
+        T.k.queue = pl->dctl;
+        T.G = pl->G;
+        T.W = pl->W;
+        T.nteams = pl->nteams;
+        T.npanels = (pl->nrhs + pl->W - 1) / pl->W;
+        T.pairs_max = pl->pairs_max;
+        T.rows_max = pl->rows_max;
+        T.team_bytes = pl->slot_bytes;
+        T.vec_stride = pl->Mp * pl->W;
+        T.tws = pl->dws;
+        T.sync = pl->dctl + 32;
+        T.part = pl->dpart;
+        T.pstride = pl->pstride;
+        T.abort_flag = pl->dctl + 1;
+        T.spin_ticks = pl->spin_ticks;
+        HIP_TRY(scocg::launch_team(T, P->bd, pl->gal, pl->variant, pl->nt, pl->slots, pl->team_lds, st));
+        return SCOCG_OK;
+    }
     HIP_TRY(scocg::launch_fill_i32(pl->dqueue, 0, 1, st));
-    if (pl->qmr) HIP_TRY(scocg::launch_qmr(k, P->bd, !P->has_S, pl->gal, pl->dl, pl->unit, pl->nt, pl->slots, st));
+    if (pl->qmr)
+        HIP_TRY(scocg::launch_qmr(k, P->bd, !P->has_S, pl->gal, pl->dl, pl->unit && pl->dl, pl->nt, pl->slots, st));
     else HIP_TRY(scocg::launch_solver(k, P->bd, pl->proj ? 3 : pl->prec, !P->has_S, pl->nt, pl->slots, st));
     return SCOCG_OK;
 }
@@ -1040,6 +1158,12 @@ extern "C" scocg_status scocg_plan_stats(scocg_plan* pl, int64_t* stats) {
     if (pl->last_stream) HIP_TRY(hipStreamSynchronize(pl->last_stream));
     else HIP_TRY(hipDeviceSynchronize());
     HIP_TRY(hipMemcpy(stats, pl->dstats, sizeof(int64_t) * scocg::NSTAT * pl->nrhs, hipMemcpyDeviceToHost));
+    if (pl->team) {
+        int32_t ab = 0;
+        HIP_TRY(hipMemcpy(&ab, pl->dctl + 1, sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (ab) return fail(SCOCG_E_DEVICE, "a wait between the workgroups of a team exceeded its bound; "
+                                            "the run was abandoned (status ABORTED)");
+    }
     return SCOCG_OK;
 }
 
@@ -1216,6 +1340,7 @@ extern "C" scocg_status scocg_autotune(scocg_problem* P, const scocg_options* op
         for (int per_cu = 1; per_cu <= 2 && result == SCOCG_OK; ++per_cu) {
             scocg_options o = opt;
             o.maxiter = probe_iters;
+            o.team_size = -1;                  // this search is over the one-workgroup solver's launch
             o.threads = threads_c[ti];
             o.slots = std::max(1, std::min(nrhs, cus * per_cu));
             scocg_plan* pl = nullptr;
@@ -1253,6 +1378,105 @@ extern "C" scocg_status scocg_autotune(scocg_problem* P, const scocg_options* op
     *best_threads = bt;
     *best_slots = bs;
     if (best_seconds) *best_seconds = best / 1e3;
+    return SCOCG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner of the team solver: panel width x workgroups per team x workgroup size
+// ---------------------------------------------------------------------------
+namespace {
+// One timed probe of a plan (warm-up, then one run); ms < 0 if the plan could not be made.
+scocg_status probe_plan(scocg_problem* P, const scocg_options& o, int32_t nshift, const scocg_z* shifts,
+                        int32_t nrhs, const int32_t* rhs_index, const scocg_rhs_spec* spec, hipStream_t st,
+                        hipEvent_t e0, hipEvent_t e1, float* ms, scocg_options* used) {
+    *ms = -1.f;
+    scocg_plan* pl = nullptr;
+    scocg_status s2 = scocg_plan_create(P, &o, nshift, shifts, nrhs, rhs_index, spec, &pl);
+    if (s2 == SCOCG_E_UNSUPPORTED || s2 == SCOCG_E_NOMEM) return SCOCG_OK;   // not a candidate here
+    if (s2 < 0) return s2;
+    scocg_z* dout = nullptr;
+    if (hipMalloc((void**)&dout, sizeof(scocg_z) * std::max<int64_t>(1, pl->out_count)) != hipSuccess) {
+        scocg_plan_free(pl);
+        return fail(SCOCG_E_NOMEM, "autotune output buffer");
+    }
+    hipError_t he = hipSuccess;
+    if ((s2 = scocg_plan_run(pl, st, dout, nullptr, nullptr, nullptr)) == SCOCG_OK &&
+        (he = hipStreamSynchronize(st)) == hipSuccess && (he = hipEventRecord(e0, st)) == hipSuccess &&
+        (s2 = scocg_plan_run(pl, st, dout, nullptr, nullptr, nullptr)) == SCOCG_OK &&
+        (he = hipEventRecord(e1, st)) == hipSuccess && (he = hipEventSynchronize(e1)) == hipSuccess) {
+        he = hipEventElapsedTime(ms, e0, e1);
+    }
+    *used = o;
+    used->threads = pl->nt;
+    used->slots = pl->slots;
+    used->team_size = pl->team ? pl->G : -1;
+    used->panel_width = pl->team ? pl->W : 1;
+    if (pl->team) {
+        int32_t ab = 0;
+        if (he == hipSuccess) he = hipMemcpy(&ab, pl->dctl + 1, sizeof(int32_t), hipMemcpyDeviceToHost);
+        if (ab) *ms = -1.f;     // an abandoned run is no candidate
+    }
+    dev_free(dout);
+    scocg_plan_free(pl);
+    if (s2 != SCOCG_OK) return s2;
+    if (he != hipSuccess) return fail(SCOCG_E_DEVICE, "autotune: %s", hipGetErrorString(he));
+    return SCOCG_OK;
+}
+}  // namespace
+
+extern "C" scocg_status scocg_autotune_team(scocg_problem* P, const scocg_options* opt_in, int32_t nshift,
+                                            const scocg_z* shifts, int32_t nrhs, const int32_t* rhs_index,
+                                            const scocg_rhs_spec* spec, int32_t probe_iters, scocg_options* best,
+                                            double* best_seconds) {
+    if (!P || !best) return fail(SCOCG_E_ARG, "NULL argument");
+    if (probe_iters <= 0) return fail(SCOCG_E_ARG, "probe_iters must be > 0");
+    scocg_options opt;
+    if (opt_in) opt = *opt_in; else scocg_options_default(&opt);
+    if (opt.method != SCOCG_METHOD_QMR && opt.method != SCOCG_METHOD_COCG_LANCZOS)
+        return fail(SCOCG_E_ARG, "the team solver runs the Lanczos-basis methods");
+    HIP_TRY(hipSetDevice(P->device));
+    const bool global = !(spec && spec->cluster_ptr);
+    struct Cand { int W, G, nt; };
+    std::vector<Cand> cands = {{1, -1, 1024}, {1, -1, 512}};
+    if (global && P->bd == 4) {
+        const Cand c4[] = {{8, 8, 1024}, {8, 8, 512}, {8, 16, 1024}, {4, 8, 512}, {4, 4, 512}, {8, 4, 1024}};
+        cands.insert(cands.end(), std::begin(c4), std::end(c4));
+    } else {
+        const Cand c1[] = {{1, 2, 512}, {1, 4, 512}, {1, 8, 512}, {1, 4, 1024}, {1, 8, 1024}};
+        cands.insert(cands.end(), std::begin(c1), std::end(c1));
+    }
+    hipStream_t st = nullptr;
+    HIP_TRY(hipStreamCreate(&st));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float bestms = 1e30f;
+    scocg_status result = SCOCG_OK;
+    bool found = false;
+    for (const Cand& c : cands) {
+        scocg_options o = opt;
+        o.maxiter = probe_iters;
+        o.panel_width = c.W;
+        o.team_size = c.G;
+        o.threads = c.nt;
+        o.slots = 0;
+        float ms = -1.f;
+        scocg_options used;
+        result = probe_plan(P, o, nshift, shifts, nrhs, rhs_index, spec, st, e0, e1, &ms, &used);
+        if (result != SCOCG_OK) break;
+        if (ms >= 0.f && ms < bestms) {
+            bestms = ms;
+            *best = used;
+            best->maxiter = opt.maxiter;
+            found = true;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(st);
+    if (result != SCOCG_OK) return result;
+    if (!found) return fail(SCOCG_E_UNSUPPORTED, "no launch shape fits this problem");
+    if (best_seconds) *best_seconds = bestms / 1e3;
     return SCOCG_OK;
 }
 

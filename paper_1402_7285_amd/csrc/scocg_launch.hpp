@@ -4,6 +4,7 @@
 #include <stddef.h>
 
 #include "scocg_params.hpp"
+#include "team_params.hpp"
 
 namespace scocg {
 
@@ -27,5 +28,13 @@ hipError_t launch_integrate(const double* G, const double* z, const double* w, c
                             const int64_t* out_off, const int32_t* out_local, int nrhs, int K, double mu, double kT,
                             double* rho, double* ldos, hipStream_t st);
 hipError_t launch_cohp(const double* h, const double* rho, double* cohp, int64_t n, hipStream_t st);
+// Team (panel) solver on the real S-Lanczos basis (team_kernels.hip): G workgroups per panel of W RHS.
+size_t team_lds_bytes(int nt, int W, int pairs, int rows_max, bool dl);
+int64_t team_ws_bytes(int W, int K, int64_t Mp, int64_t nIp, bool qmr);
+// variant: 0 S = I, 1 inner CG direction in LDS, 2 the same with S = I + off-diagonal blocks, 3 direction in HBM
+hipError_t launch_team(const TParams& T, int bd, bool gal, int variant, int nt, int grid, size_t lds,
+                       hipStream_t st);
+// resident workgroups of that kernel per compute unit
+hipError_t team_occupancy(int bd, bool gal, int variant, int nt, int W, size_t lds, int* per_cu);
 
 }  // namespace scocg
