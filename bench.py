@@ -197,16 +197,20 @@ def measure_form(B, P, prob, kw, args, method, stream, warmup, steps, warm_budge
     one each); the counts actually run are returned."""
     import torch
     threads, slots, tuned = args.threads, args.slots, None
-    if not args.no_autotune and not args.threads and not args.slots:
+    lanczos = method in ("qmr", "cocg-lanczos")
+    team = dict(team_size=args.team, panel_width=args.panel) if lanczos else {}
+    if not args.no_autotune and not args.threads and not args.slots and not (lanczos and (args.team or args.panel)):
         tuned = B.autotune(P, prob.shifts, prob.rhs, probe_iters=50,
                            cache_path=os.path.join(ROOT, "paper_1402_7285_amd", "autotune_cache.json"),
                            key_extra=f"{args.workload}|{args.nrhs}", tol=args.tol, precision=PREC[args.precision],
                            projected=args.projected, method=METHODS[method], **kw)
         threads, slots = tuned["threads"], tuned["slots"]
+        if lanczos and "team_size" in tuned:
+            team = dict(team_size=tuned["team_size"], panel_width=tuned["panel_width"])
         print(f"[bench] {method}: autotuned {tuned}", file=sys.stderr, flush=True)
     plan = B.Plan(P, prob.shifts, prob.rhs, tol=args.tol, precision=PREC[args.precision], audit=1,
                   threads=threads, slots=slots, projected=args.projected, maxiter=args.maxiter,
-                  method=METHODS[method], **kw)
+                  method=METHODS[method], **team, **kw)
     projected = bool(plan.info["global"] & 2)
     qmr = bool(plan.info["global"] & 4)
     gal = bool(plan.info["global"] & 8)
@@ -256,7 +260,10 @@ def measure_form(B, P, prob, kw, args, method, stream, warmup, steps, warm_budge
     stats = plan.stats()
     ms_per_step = wall / n_steps * 1e3
     nout = np.diff(prob.out_ptr)
-    w_share = min(plan.info["slots"], prob.nrhs) if prob.cluster_ptr is None else 1
+    # RHS sharing the blocks at once: every resident RHS of a global system (a team holds W of them
+    # on team_size workgroups), 1 for order-N clusters
+    resident = plan.info["slots"] // plan.info["team_size"] * plan.info["panel_width"]
+    w_share = min(resident, prob.nrhs) if prob.cluster_ptr is None else 1
     if qmr:
         alg = algorithmic_bytes_qmr(stats, nout, prob.bdim, prob.S is not None, w_share, gal)
     else:
@@ -271,7 +278,8 @@ def measure_form(B, P, prob, kw, args, method, stream, warmup, steps, warm_budge
         "fallback_iterations": int(stats[:, 7].sum()),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args, form_key, alg),
-                     "kernel": "k_sqmr (persistent solver)" if qmr else "k_scocg (persistent solver)",
+                     "kernel": ("k_team (team solver)" if plan.info["global"] & 64 else
+                                "k_sqmr (persistent solver)" if qmr else "k_scocg (persistent solver)"),
                      "kernel_ms": kernel_s * 1e3, "algorithmic_bytes": alg},
     }
     form = ("COCG iterates on the real Lanczos basis, requested rows" if gal else
@@ -482,6 +490,9 @@ def main():
                          "cocg-lanczos: the COCG iterates on that basis")
     ap.add_argument("--copy-calib", type=int, default=0, help="only run a device copy of this many bytes")
     ap.add_argument("--no-autotune", action="store_true", help="use --threads/--slots as given")
+    ap.add_argument("--team", type=int, default=0,
+                    help="Lanczos-basis forms: workgroups per team (-1 one-workgroup solver, 0 autotuned)")
+    ap.add_argument("--panel", type=int, default=0, help="Lanczos-basis forms: RHS per panel (0 autotuned)")
     ap.add_argument("--no-companion", action="store_true",
                     help="do not also time the seed-switching COCG form when --method is another form")
     ap.add_argument("--plain", type=int, default=0,
@@ -536,6 +547,9 @@ def main():
                    "M": prob.M, "tol": args.tol, "precision": args.precision, "batched": "persistent",
                    "slots": plan.info["slots"], "threads": plan.info["threads"], "form": r["form"],
                    "lds_bytes": plan.info["lds_bytes"], "cg_direction_in_lds": bool(plan.info["global"] & 16),
+                   "team_size": plan.info["team_size"], "panel_width": plan.info["panel_width"],
+                   "matrix_cores": bool(plan.info["global"] & 128),
+                   "cg_vectors_in_registers": bool(plan.info["global"] & 256),
                    "autotuned": r["autotuned"], "steps_requested": args.steps, "warmup_requested": args.warmup,
                    "time_budget_s": args.time_budget},
         **r["report"],

@@ -198,11 +198,17 @@ typedef struct {
                                4x4 blocks and every RHS on the whole system; with 4x4
                                blocks the block products then run on FP64 matrix
                                cores); 0 = chosen by the library. */
+    int32_t team_registers; /* team solver with S != I, 4x4 blocks and a panel of 4 or 8:
+                               1 (default) keeps the inner CG's direction, solution
+                               and S-product in registers and its residual on the
+                               workgroup's rows in LDS when a compiled instance
+                               covers the workgroup's share of rows; 0 keeps them
+                               in memory (the direction in LDS). */
 } scocg_options;
 
 /* Defaults: tol 1e-10, maxiter 0, FP64, replace_every 0, inner_maxiter 1000,
  * inner_tol 1e-13, inner_tol_lo 1e-6, seed_index -1, threads 0, slots 0, audit 1,
- * projected 1, method COCG, team_size 0, panel_width 0. */
+ * projected 1, method COCG, team_size 0, panel_width 0, team_registers 1. */
 void scocg_options_default(scocg_options* opt);
 
 /* ---- right-hand sides ----------------------------------------------------- */
@@ -265,7 +271,8 @@ int64_t scocg_plan_out_count(const scocg_plan* plan);
  * diagonal blocks, S is applied as I plus a plan-held copy of its nonzero
  * off-diagonal blocks; bit 6: the team solver runs (then [0] is the number of
  * workgroups of all teams and [3] the bytes of one team's working memory);
- * bit 7: its block products run on FP64 matrix cores.  [8] workgroups per
+ * bit 7: its block products run on FP64 matrix cores; bit 8: its inner CG
+ * keeps its vectors in registers and LDS.  [8] workgroups per
  * team (1 for the other solvers), [9] panel width (right-hand sides per team).
  */
 #define SCOCG_NINFO 10

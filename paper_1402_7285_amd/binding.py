@@ -53,7 +53,7 @@ class scocg_options(C.Structure):
                 ("replace_every", C.c_int32), ("inner_maxiter", C.c_int32), ("inner_tol", C.c_double),
                 ("inner_tol_lo", C.c_double), ("seed_index", C.c_int32), ("threads", C.c_int32),
                 ("slots", C.c_int32), ("audit", C.c_int32), ("projected", C.c_int32), ("method", C.c_int32),
-                ("team_size", C.c_int32), ("panel_width", C.c_int32)]
+                ("team_size", C.c_int32), ("panel_width", C.c_int32), ("team_registers", C.c_int32)]
 
 
 class scocg_rhs_spec(C.Structure):

@@ -18,6 +18,11 @@ HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # keep the compiler from emitting packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no loop strength reduction and no machine-level loop-invariant hoisting: both keep one 64-bit
+    # address per strided array access live across the solvers' long loops, which pushes the
+    # 1024-thread kernels (128 VGPRs) into private-memory spills; recomputing an address costs an
+    # integer add, a spill costs a scratch round trip (and spilling instances are never launched)
+    "-mllvm", "-disable-lsr", "-mllvm", "-disable-machine-licm",
 ]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
               "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]

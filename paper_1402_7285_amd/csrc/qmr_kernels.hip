@@ -568,7 +568,7 @@ __global__ __launch_bounds__(NT) void k_sqmr(KParams P) {
             L.ctl[1] = 0;
         }
         __syncthreads();
-        const int job = s_job;
+        const int job = __builtin_amdgcn_readfirstlane(s_job);   // uniform: its loads are scalar
         __syncthreads();
         if (job >= P.nrhs) break;
         solve_one<BD, NT, SID, GAL, DL, UNIT>(P, P.order[job], ws, L, ldsd);
@@ -605,7 +605,35 @@ static hipError_t launch_bd(const KParams& P, bool sid, bool gal, bool dl, bool 
     return launch_nt<BD, 512>(P, sid, gal, dl, unit, slots, st);
 }
 
+template <int BD, int NT, bool SID, bool GAL, bool DL, bool UNIT>
+static size_t priv_one() {
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, (const void*)k_sqmr<BD, NT, SID, GAL, DL, UNIT>) != hipSuccess) return (size_t)-1;
+    return fa.localSizeBytes;
+}
+template <int BD, int NT, bool GAL>
+static size_t priv_var(bool sid, bool dl, bool unit) {
+    if (sid) return priv_one<BD, NT, true, GAL, false, false>();
+    if (dl) return unit ? priv_one<BD, NT, false, GAL, true, true>() : priv_one<BD, NT, false, GAL, true, false>();
+    return priv_one<BD, NT, false, GAL, false, false>();
+}
+template <int BD>
+static size_t priv_bd(bool sid, bool gal, bool dl, bool unit, int nt) {
+    if (nt == 256) return gal ? priv_var<BD, 256, true>(sid, dl, unit) : priv_var<BD, 256, false>(sid, dl, unit);
+    if (nt == 1024) return gal ? priv_var<BD, 1024, true>(sid, dl, unit) : priv_var<BD, 1024, false>(sid, dl, unit);
+    return gal ? priv_var<BD, 512, true>(sid, dl, unit) : priv_var<BD, 512, false>(sid, dl, unit);
+}
+
 }  // namespace qmr
+
+size_t qmr_private_bytes(int bd, bool sid, bool gal, bool dl, bool unit, int nt) {
+    switch (bd) {
+        case 1: return qmr::priv_bd<1>(sid, gal, dl, unit, nt);
+        case 4: return qmr::priv_bd<4>(sid, gal, dl, unit, nt);
+        case 9: return qmr::priv_bd<9>(sid, gal, dl, unit, nt);
+        default: return (size_t)-1;
+    }
+}
 
 size_t qmr_lds_bytes(int K, int nt, int64_t Mp, bool dl) {
     return dl ? qmr::lds_dir_offset(K, nt) + sizeof(double) * (size_t)Mp : qmr::lds_bytes(K, nt);

@@ -125,7 +125,7 @@ struct scocg_plan {
     bool unit = false;        // S applied as I + a copy of its off-diagonal blocks (dsrow/dscol/dsval)
     // team (panel) solver of the Lanczos-basis methods
     bool team = false;
-    int G = 1, W = 1, nteams = 0, variant = 0, pairs_max = 0, rows_max = 0, pstride = 0;
+    int G = 1, W = 1, nteams = 0, variant = 0, ri = 0, pairs_max = 0, rows_max = 0, pstride = 0;
     bool team_dl = false;
     size_t team_lds = 0;
     int64_t spin_ticks = 0;
@@ -509,6 +509,7 @@ extern "C" void scocg_options_default(scocg_options* o) {
     o->method = SCOCG_METHOD_COCG;
     o->team_size = 0;
     o->panel_width = 0;
+    o->team_registers = 1;
 }
 
 // Initial seed: smallest |Im z|, then Re z closest to the median of Re z
@@ -853,8 +854,26 @@ extern "C" scocg_status scocg_plan_create(scocg_problem* P, const scocg_options*
     const size_t lds = pl->qmr ? scocg::qmr_lds_bytes(nshift, pl->nt, pl->Mp, pl->dl)
                                : scocg::solver_lds_bytes(nshift, pl->nt);
     if (lds > 160 * 1024) return bail(fail(SCOCG_E_UNSUPPORTED, "too many shifts for LDS"));
+    // a workgroup size whose kernel instance would spill registers to private memory is not launched:
+    // the first of (requested, 512, 256, 1024) that keeps every value in registers runs instead
+    if (!pl->team) {
+        const int tries[4] = {pl->nt, 512, 256, 1024};
+        for (int nt : tries) {
+            const size_t dl_lds = pl->qmr ? scocg::qmr_lds_bytes(nshift, nt, pl->Mp, pl->dl) : 0;
+            if (pl->qmr && dl_lds > 160 * 1024) continue;
+            const size_t priv = pl->qmr ? scocg::qmr_private_bytes(P->bd, !P->has_S, pl->gal, pl->dl,
+                                                                    pl->unit && pl->dl, nt)
+                                        : scocg::solver_private_bytes(P->bd, pl->proj ? 3 : pl->prec, !P->has_S, nt);
+            if (priv == 0) {
+                pl->nt = nt;
+                break;
+            }
+        }
+    }
+    const size_t lds_nt = pl->qmr ? scocg::qmr_lds_bytes(nshift, pl->nt, pl->Mp, pl->dl)
+                                  : scocg::solver_lds_bytes(nshift, pl->nt);
     int per_cu = std::max(1, 2048 / pl->nt);
-    per_cu = std::min<int>(per_cu, (int)std::max<size_t>(1, (160 * 1024) / lds));
+    per_cu = std::min<int>(per_cu, (int)std::max<size_t>(1, (160 * 1024) / lds_nt));
     per_cu = std::min(per_cu, 2);
     int slots = opt.slots ? opt.slots : cus * per_cu;
     slots = std::max(1, std::min(slots, std::max(1, nrhs)));
@@ -901,13 +920,19 @@ extern "C" scocg_status scocg_plan_create(scocg_problem* P, const scocg_options*
         if (W > 1 && !can_panel)
             return bail(fail(SCOCG_E_UNSUPPORTED, "panels of several RHS need 4x4 blocks and the whole system"));
         if (G > 32) return bail(fail(SCOCG_E_ARG, "team_size must be -1 .. 32"));
-        if (W == 0) W = can_panel ? (nrhs >= 64 ? 8 : (nrhs >= 16 ? 4 : 1)) : 1;
+        // Chosen by the library: the one-workgroup solver whenever the right-hand sides alone fill the
+        // compute units (measured faster there: every workgroup then streams its own vectors without team
+        // waits); teams when there are fewer RHS than compute units on a large system, or order-N
+        // clusters large enough that one workgroup per RHS would bound the launch by its latency.
+        const bool auto_shape = G == 0 && W == 0;
+        if (W == 0) W = can_panel && nrhs < cus ? (nrhs >= 64 ? 8 : (nrhs >= 16 ? 4 : 1)) : 1;
         const int npanels = (nrhs + W - 1) / W;
         if (G == 0) {
             if (pl->global) {
                 // enough teams to fill the compute units, at least 64 block rows per workgroup
                 G = 1;
                 while (G < 8 && (int64_t)npanels * G * 2 <= cus && P->nb >= (int64_t)G * 2 * 64) G *= 2;
+                if (auto_shape && nrhs >= cus) G = 1;
             } else {
                 G = hm.maxM >= 6144 ? 8 : (hm.maxM >= 3072 ? 4 : (hm.maxM >= 1536 ? 2 : 1));
             }
@@ -918,21 +943,61 @@ extern "C" scocg_status scocg_plan_create(scocg_problem* P, const scocg_options*
             pl->team = true;
             pl->G = G;
             pl->W = W;
-            pl->nt = opt.threads ? opt.threads : (W >= 8 ? 1024 : 512);
             pl->pairs_max = (W * nshift + G - 1) / G;
             int64_t maxshare = 0;
             for (const auto& sy : hm.sys) maxshare = std::max<int64_t>(maxshare, ((int64_t)sy.nrows + G - 1) / G);
             pl->rows_max = (int)(maxshare * P->bd);
             // 160 KB of LDS per workgroup, less the kernel's own few static words
             const size_t lds_cap = 160 * 1024 - 256;
-            pl->team_dl = P->has_S && scocg::team_lds_bytes(pl->nt, W, pl->pairs_max, pl->rows_max, true) <= lds_cap;
-            pl->team_lds = scocg::team_lds_bytes(pl->nt, W, pl->pairs_max, pl->rows_max, pl->team_dl);
-            if (pl->team_lds > lds_cap) return bail(fail(SCOCG_E_UNSUPPORTED, "too many shifts for LDS"));
-            pl->variant = !P->has_S ? 0 : (pl->team_dl ? (pl->unit ? 2 : 1) : 3);
+            pl->team_dl = P->has_S && scocg::team_lds_bytes(512, W, pl->pairs_max, pl->rows_max, true) <= lds_cap;
+            // Launch shapes in order of preference; the first whose kernel fits a compute unit and keeps
+            // every value in registers (no scratch: private-memory spills are never launched) is taken.
+            // (threads is a request: the other size runs if the requested one would spill or not fit)
+            std::vector<int> nts;
+            if (opt.threads) nts = {opt.threads, opt.threads == 1024 ? 512 : 1024};
+            else if (W >= 8) nts = {1024, 512};
+            else nts = {512, 1024};
             int per_cu = 0;
-            if (scocg::team_occupancy(P->bd, pl->gal, pl->variant, pl->nt, W, pl->team_lds, &per_cu) != hipSuccess ||
-                per_cu < 1)
-                return bail(fail(SCOCG_E_UNSUPPORTED, "team kernel does not fit a compute unit"));
+            bool found = false;
+            for (int nt : nts) {
+                for (int rv = opt.team_registers ? 1 : 0; rv >= 0 && !found; --rv) {
+                    int variant = !P->has_S ? 0 : (pl->team_dl ? (pl->unit ? 2 : 1) : 3);
+                    int ri = 0;
+                    size_t lds = scocg::team_lds_bytes(nt, W, pl->pairs_max, pl->rows_max, pl->team_dl);
+                    if (rv) {
+                        // the inner CG's vectors in registers (its residual in the LDS region of the direction)
+                        // when a compiled instance covers this workgroup's share of block rows
+                        if (!(P->has_S && pl->team_dl && P->bd == 4 && W % 4 == 0)) continue;
+                        const int nw = nt / 64;
+                        const int need = (int)((maxshare + 4 * nw - 1) / (4 * nw));
+                        const size_t lds_rv = scocg::team_lds_bytes(nt, W, pl->pairs_max, pl->rows_max, true, true);
+                        for (int r : {4, 8, 16})
+                            if (r >= need && scocg::team_rv_ok(nt, W, r) && lds_rv <= lds_cap) {
+                                ri = r;
+                                break;
+                            }
+                        if (!ri) continue;
+                        variant = pl->unit ? 4 : 5;
+                        lds = lds_rv;
+                    }
+                    if (lds > lds_cap) continue;
+                    int pc = 0;
+                    size_t priv = 0;
+                    if (scocg::team_occupancy(P->bd, pl->gal, variant, ri, nt, W, lds, &pc, &priv) != hipSuccess ||
+                        pc < 1 || priv > 0)
+                        continue;
+                    pl->nt = nt;
+                    pl->variant = variant;
+                    pl->ri = ri;
+                    pl->team_lds = lds;
+                    per_cu = pc;
+                    found = true;
+                }
+                if (found) break;
+            }
+            if (!found)
+                return bail(fail(SCOCG_E_UNSUPPORTED, "no team launch shape for this problem fits a compute unit "
+                                                      "without private-memory spills (threads %d)", opt.threads));
             const int maxwg = cus * per_cu;
             if (G > maxwg) return bail(fail(SCOCG_E_UNSUPPORTED, "team larger than the resident workgroups"));
             int nteams = std::min(npanels, maxwg / G);
@@ -1018,10 +1083,10 @@ extern "C" scocg_status scocg_plan_info(const scocg_plan* pl, int64_t* info) {
                                 : scocg::solver_lds_bytes(pl->K, pl->nt));
     info[6] = pl->prec;
     const bool dl = pl->team ? pl->team_dl : pl->dl;
-    const bool unit = pl->team ? pl->variant == 2 : (pl->unit && pl->dl);
+    const bool unit = pl->team ? (pl->variant == 2 || pl->variant == 4) : (pl->unit && pl->dl);
     const bool mfma = pl->team && pl->P->bd == 4 && pl->W % 4 == 0;
     info[7] = (pl->global ? 1 : 0) | (pl->proj ? 2 : 0) | (pl->qmr ? 4 : 0) | (pl->gal ? 8 : 0) | (dl ? 16 : 0) |
-              (unit ? 32 : 0) | (pl->team ? 64 : 0) | (mfma ? 128 : 0);
+              (unit ? 32 : 0) | (pl->team ? 64 : 0) | (mfma ? 128 : 0) | (pl->team && pl->ri ? 256 : 0);
     if (pl->team) info[5] = (int64_t)pl->team_lds;
     info[8] = pl->team ? pl->G : 1;
     info[9] = pl->team ? pl->W : 1;
@@ -1119,7 +1184,7 @@ extern "C" scocg_status scocg_plan_run(scocg_plan* pl, void* stream, scocg_z* ou
         T.pstride = pl->pstride;
         T.abort_flag = pl->dctl + 1;
         T.spin_ticks = pl->spin_ticks;
-        HIP_TRY(scocg::launch_team(T, P->bd, pl->gal, pl->variant, pl->nt, pl->slots, pl->team_lds, st));
+        HIP_TRY(scocg::launch_team(T, P->bd, pl->gal, pl->variant, pl->ri, pl->nt, pl->slots, pl->team_lds, st));
         return SCOCG_OK;
     }
     HIP_TRY(scocg::launch_fill_i32(pl->dqueue, 0, 1, st));
@@ -1363,7 +1428,7 @@ extern "C" scocg_status scocg_autotune(scocg_problem* P, const scocg_options* op
                 (s2 = scocg_plan_run(pl, st, dout, nullptr, nullptr, nullptr)) == SCOCG_OK &&
                 (he = hipEventRecord(e1, st)) == hipSuccess && (he = hipEventSynchronize(e1)) == hipSuccess &&
                 (he = hipEventElapsedTime(&ms, e0, e1)) == hipSuccess) {
-                if (ms < best) { best = ms; bt = o.threads; bs = o.slots; }
+                if (ms < best) { best = ms; bt = pl->nt; bs = o.slots; }
             }
             dev_free(dout);
             scocg_plan_free(pl);

@@ -1014,7 +1014,7 @@ __global__ __launch_bounds__(NT) void k_scocg(KParams P) {
     for (;;) {
         if (threadIdx.x == 0) s_job = atomicAdd(P.queue, 1);
         __syncthreads();
-        const int job = s_job;
+        const int job = __builtin_amdgcn_readfirstlane(s_job);   // uniform: its loads are scalar
         __syncthreads();
         if (job >= P.nrhs) break;
         if constexpr (PROJ) solve_one_proj<BD, NT, SID>(P, P.order[job], ws, L);
@@ -1076,6 +1076,35 @@ hipError_t launch_solver(const KParams& P, int bd, int prec, bool sid, int nt, i
         case 4: return launch_nt<4>(P, prec, sid, nt, slots, st);
         case 9: return launch_nt<9>(P, prec, sid, nt, slots, st);
         default: return hipErrorInvalidValue;
+    }
+}
+
+// Private (scratch) bytes per lane of the instance launch_solver would run.
+template <int BD, int NT, class TV, class TB, bool SID, bool PROJ = false>
+static size_t priv_one() {
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, (const void*)k_scocg<BD, NT, TV, TB, SID, PROJ>) != hipSuccess) return (size_t)-1;
+    return fa.localSizeBytes;
+}
+template <int BD, int NT>
+static size_t priv_prec(int prec, bool sid) {
+    if (prec == 3) return sid ? priv_one<BD, NT, double, double, true, true>() : priv_one<BD, NT, double, double, false, true>();
+    if (prec == 0) return sid ? priv_one<BD, NT, double, double, true>() : priv_one<BD, NT, double, double, false>();
+    if (prec == 1) return sid ? priv_one<BD, NT, float, float, true>() : priv_one<BD, NT, float, float, false>();
+    return sid ? priv_one<BD, NT, float, bf16_t, true>() : priv_one<BD, NT, float, bf16_t, false>();
+}
+template <int BD>
+static size_t priv_nt(int prec, bool sid, int nt) {
+    if (nt == 256) return priv_prec<BD, 256>(prec, sid);
+    if (nt == 1024) return priv_prec<BD, 1024>(prec, sid);
+    return priv_prec<BD, 512>(prec, sid);
+}
+size_t solver_private_bytes(int bd, int prec, bool sid, int nt) {
+    switch (bd) {
+        case 1: return priv_nt<1>(prec, sid, nt);
+        case 4: return priv_nt<4>(prec, sid, nt);
+        case 9: return priv_nt<9>(prec, sid, nt);
+        default: return (size_t)-1;
     }
 }
 

@@ -17,6 +17,10 @@ int64_t solver_slot_bytes_proj(int K, int64_t Mp, int64_t nIp);
 // prec: 0 FP64, 1 FP32, 2 FP32 compute with bfloat16 blocks, 3 projected FP64; sid: S = I.
 hipError_t launch_solver(const KParams& P, int bd, int prec, bool sid, int nt, int slots, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
+// Private (scratch) bytes per lane of the instance the one-workgroup launchers would run
+// ((size_t)-1 if it cannot be queried); instances with spills are not launched.
+size_t solver_private_bytes(int bd, int prec, bool sid, int nt);
+size_t qmr_private_bytes(int bd, bool sid, bool gal, bool dl, bool unit, int nt);
 // Shifted QMR over the real S-Lanczos basis (qmr_kernels.hip).
 size_t qmr_lds_bytes(int K, int nt, int64_t Mp, bool dl);
 int64_t qmr_slot_bytes(int K, int64_t Mp, int64_t nIp);
@@ -29,12 +33,17 @@ hipError_t launch_integrate(const double* G, const double* z, const double* w, c
                             double* rho, double* ldos, hipStream_t st);
 hipError_t launch_cohp(const double* h, const double* rho, double* cohp, int64_t n, hipStream_t st);
 // Team (panel) solver on the real S-Lanczos basis (team_kernels.hip): G workgroups per panel of W RHS.
-size_t team_lds_bytes(int nt, int W, int pairs, int rows_max, bool dl);
+size_t team_lds_bytes(int nt, int W, int pairs, int rows_max, bool dl, bool rv = false);
 int64_t team_ws_bytes(int W, int K, int64_t Mp, int64_t nIp, bool qmr);
-// variant: 0 S = I, 1 inner CG direction in LDS, 2 the same with S = I + off-diagonal blocks, 3 direction in HBM
-hipError_t launch_team(const TParams& T, int bd, bool gal, int variant, int nt, int grid, size_t lds,
+// variant: 0 S = I, 1 inner CG direction in LDS, 2 the same with S = I + off-diagonal blocks, 3 direction in
+// HBM, 4 / 5 the inner CG's vectors in registers (ri block-row quads per wave) with S = I + off-diagonal
+// blocks / S as stored
+hipError_t launch_team(const TParams& T, int bd, bool gal, int variant, int ri, int nt, int grid, size_t lds,
                        hipStream_t st);
-// resident workgroups of that kernel per compute unit
-hipError_t team_occupancy(int bd, bool gal, int variant, int nt, int W, size_t lds, int* per_cu);
+// resident workgroups of that kernel per compute unit, and its private (scratch) bytes per lane
+hipError_t team_occupancy(int bd, bool gal, int variant, int ri, int nt, int W, size_t lds, int* per_cu,
+                          size_t* private_bytes);
+// whether the register-resident form is compiled for (threads, panel width, block-row quads per wave)
+bool team_rv_ok(int nt, int W, int ri);
 
 }  // namespace scocg

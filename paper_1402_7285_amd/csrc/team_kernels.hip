@@ -43,6 +43,8 @@
 // second reduction: two waits per CG step.
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "scocg_device.hpp"
 #include "scocg_params.hpp"
 #include "team_params.hpp"
@@ -264,10 +266,13 @@ struct Sys {
 
 // y = A x (+ x if UNIT) on the owned elements of block rows [a0, a1);
 // ep(row, slot, col, ldsidx, y) receives each result.  x is [M][W] and was
-// published by the team (device-coherent loads).
-template <int BD, int NT, int W, bool UNIT, class EP>
+// published by the team (device-coherent loads).  LX (matrix-core layout
+// only): the workgroup's own rows of x are read from LDS instead (xl,
+// [rows][W] in the workgroup's local order).
+template <int BD, int NT, int W, bool UNIT, class EP, bool LX = false>
 __device__ __forceinline__ void spmm(const double* __restrict__ A, const Sys& sy, int a0, int a1,
-                                     const double* __restrict__ x, EP ep) {
+                                     const double* __restrict__ x, EP ep, const double* xl = nullptr) {
+    static_assert(!LX || Lay<BD, NT, W>::MF, "LDS rows in the matrix-core layout only");
     using L = Lay<BD, NT, W>;
     const int tid = threadIdx.x;
     const bool direct = sy.egid == nullptr;
@@ -304,8 +309,12 @@ __device__ __forceinline__ void spmm(const double* __restrict__ A, const Sys& sy
 #pragma unroll
                 for (int u = 0; u < CH; ++u) {
                     const double* xb = x + ((int64_t)col[u] * 4 + hi2) * W + lo2;   // B operand: k = hi2, col lo2
+                    const bool own = LX && col[u] >= a0 && col[u] < a1;
 #pragma unroll
-                    for (int s = 0; s < L::NS; ++s) bv[u][s] = ld_pub(xb + 4 * s);
+                    for (int s = 0; s < L::NS; ++s) {
+                        if (own) bv[u][s] = xl[((col[u] - a0) * 4 + hi2) * W + 4 * s + lo2];
+                        else bv[u][s] = ld_pub(xb + 4 * s);
+                    }
                 }
 #pragma unroll
                 for (int u = 0; u < CH; ++u) {
@@ -321,7 +330,7 @@ __device__ __forceinline__ void spmm(const double* __restrict__ A, const Sys& sy
                 for (int s = 0; s < L::NS; ++s) {
                     const int col = 4 * s + lo2;
                     double y = acc[s];
-                    if constexpr (UNIT) y += ld_pub(x + (int64_t)row * W + col);
+                    if constexpr (UNIT) y += LX ? xl[li + col] : ld_pub(x + (int64_t)row * W + col);
                     ep(row, s, col, li + col, y);
                 }
             }
@@ -379,6 +388,38 @@ __device__ __forceinline__ void spmm(const double* __restrict__ A, const Sys& sy
             }
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// register-resident form (4x4 blocks, W a multiple of 4): the matrix-core
+// layout with the block-row quads of each wave unrolled (RI of them at most),
+// so that per-thread vectors can live in registers indexed [k][slot].
+// ---------------------------------------------------------------------------
+// f(integral_constant<0>), ..., f(integral_constant<N - 1>): indices known when the body is generated,
+// so that per-thread arrays indexed by them stay in registers
+template <class F, int... I>
+__device__ __forceinline__ void sfor_impl(F& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void sfor(F&& f) {
+    sfor_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// f(K, S, row, col, ldsidx) for every owned element; K and S are integral constants.
+template <int NT, int W, int RI, class F>
+__device__ __forceinline__ void for_elems_r(int a0, int a1, F f) {
+    constexpr int NW = NT / 64, NS = W / 4;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int beta = (lane >> 2) & 3, ii = lane >> 4, jj = lane & 3;
+    sfor<RI>([&](auto K) __attribute__((always_inline)) {
+        const int a = a0 + 4 * (w + NW * (int)K) + beta;
+        if (a < a1) {
+            const int row = 4 * a + ii;
+            const int li = (4 * (a - a0) + ii) * W;
+            sfor<NS>([&](auto S) __attribute__((always_inline)) { f(K, S, row, 4 * (int)S + jj, li + 4 * (int)S + jj); });
+        }
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -451,8 +492,10 @@ __host__ __device__ inline size_t lds_fixed_bytes(int NT, int W, int pairs) {
     b += 16 + 8 * sizeof(int);   // alignment of the control words, and the words
     return (b + 255) & ~(size_t)255;
 }
-__host__ __device__ inline size_t lds_bytes(int NT, int W, int pairs, int rows_max, bool dl) {
-    return lds_fixed_bytes(NT, W, pairs) + (dl ? sizeof(double) * (size_t)rows_max * W : 0);
+// dl: one region of rows_max x W doubles (the CG direction, or in the register-resident form the
+// residual); rv: a second one (the register-resident form's staging of product results)
+__host__ __device__ inline size_t lds_bytes(int NT, int W, int pairs, int rows_max, bool dl, bool rv = false) {
+    return lds_fixed_bytes(NT, W, pairs) + ((dl ? 1 : 0) + (rv ? 1 : 0)) * sizeof(double) * (size_t)rows_max * W;
 }
 
 __device__ inline Lds carve(unsigned char* q, int NT, int W, int pairs) {
@@ -504,8 +547,14 @@ __device__ __forceinline__ void col_range(int c, int K, int G, int rank, int npa
     hi = min(hi, npairs);
 }
 
-template <int BD, int NT, int W, bool SID, bool GAL, bool DL, bool UNIT>
+// RI > 0: the register-resident form (4x4 blocks, W a multiple of 4, S != I): the inner CG's
+// direction, solution and S-product live in registers, its residual on the workgroup's rows in LDS
+// (the LDS region DL would give the direction), published for the other workgroups' halo reads.
+template <int BD, int NT, int W, bool SID, bool GAL, bool DL, bool UNIT, int RI>
 __device__ bool solve_panel(const TParams& T, int panel, Team& tm, const Lds& L, int* s_flag) {
+    static_assert(RI == 0 || (BD == 4 && W % 4 == 0 && !SID && DL), "register-resident form");
+    constexpr bool RV = RI > 0;
+    constexpr int RK = RV ? RI : 1;
     using LY = Lay<BD, NT, W>;
     constexpr int NS = LY::NS;
     constexpr int NV = 2 * W;
@@ -552,6 +601,10 @@ __device__ bool solve_panel(const TParams& T, int panel, Team& tm, const Lds& L,
     double* wcg = (double*)tb + 5 * vs;       // S d
     double* dd = DL ? L.d : (double*)tb + 6 * vs + (int64_t)a0 * BD * W;   // CG direction, local index
     double2* pairmem = (double2*)((double*)tb + 7 * vs);
+    // register-resident form: the CG's direction, solution and S-product (also u = H q / beta) per element
+    double rd[RK][NS], rq[RK][NS], rw[RK][NS];
+    double* resl = L.d;                       // register-resident form: the CG residual on this workgroup's rows
+    double* ystg = L.d + (int64_t)T.rows_max * W;   // and the products' results, staged per element
 
     // ---- owned pairs: p = rank + G m < W K; column p / K, shift p % K
     const int npairs = (W * K - rank + G - 1) / G;
@@ -593,7 +646,7 @@ __device__ bool solve_panel(const TParams& T, int panel, Team& tm, const Lds& L,
     double* qB = (double*)tb + vs;
     double* tprev = (double*)tb + 2 * vs;     // t_{-1} = b
     double* tcur = (double*)tb + 3 * vs;
-    for_elems<BD, NT, W>(a0, a1, [&](int row, int s, int c, int li) {
+    for_elems<BD, NT, W>(a0, a1, [&](int row, int s, int c, int li) __attribute__((always_inline)) {
         st_pub(tprev + (int64_t)row * W + c, row == (int)COLV(L, C_BLOC, c) ? 1.0 : 0.0);
     });
     double* qcur = SID ? tprev : qA;
@@ -601,8 +654,8 @@ __device__ bool solve_panel(const TParams& T, int panel, Team& tm, const Lds& L,
 
     // S q = rhs by CG for the active columns (rhs published, [M][W]); q left in
     // qout with ordinary stores on the workgroup's rows; C_CGIT = steps taken.
-    auto inner_cg = [&](const double* rhs, double* qout) -> bool {
-        for_elems<BD, NT, W>(a0, a1, [&](int row, int s, int c, int li) {
+    auto inner_cg = [&](const double* rhs, double* qout) __attribute__((always_inline)) -> bool {
+        for_elems<BD, NT, W>(a0, a1, [&](int row, int s, int c, int li) __attribute__((always_inline)) {
             const double v = ld_pub(rhs + (int64_t)row * W + c);
             ures[(int64_t)row * W + c] = v;
             dd[li] = v;
@@ -627,7 +680,7 @@ __device__ bool solve_panel(const TParams& T, int panel, Team& tm, const Lds& L,
 #pragma unroll
             for (int s = 0; s < NS; ++s) acc[s] = 0.0;
             spmm<BD, NT, W, UNIT>(Sb, syS, a0, a1, m == 0 ? rhs : ures,
-                                  [&](int row, int s, int c, int li, double y) {
+                                  [&](int row, int s, int c, int li, double y) __attribute__((always_inline)) {
                 if (COLV(L, C_CGACT, c) == 0.0) return;
                 const int64_t gi = (int64_t)row * W + c;
                 double dv, wv;
@@ -653,7 +706,7 @@ __device__ bool solve_panel(const TParams& T, int panel, Team& tm, const Lds& L,
             // (b) q += a d, r -= a w (published), ||r||^2
 #pragma unroll
             for (int s = 0; s < NS; ++s) acc[s] = 0.0;
-            for_elems<BD, NT, W>(a0, a1, [&](int row, int s, int c, int li) {
+            for_elems<BD, NT, W>(a0, a1, [&](int row, int s, int c, int li) __attribute__((always_inline)) {
                 if (COLV(L, C_CGACT, c) == 0.0) return;
                 const double a = COLV(L, C_A, c);
                 const int64_t gi = (int64_t)row * W + c;
@@ -680,10 +733,106 @@ __device__ bool solve_panel(const TParams& T, int panel, Team& tm, const Lds& L,
         return true;
     };
 
+    // The same CG with its vectors in registers and its residual in LDS (resl, published in ures for
+    // the other workgroups); the solution is left in rq.
+    // the products' results go to LDS (the same thread reads each back in the register pass)
+    auto stage = [&](int row, int s, int c, int li, double y) __attribute__((always_inline)) { ystg[li] = y; };
+    auto inner_cg_r = [&](const double* rhs) __attribute__((always_inline)) -> bool {
+        if constexpr (RV) {
+            // every register element starts defined (also those a thread does not own), so that none is
+            // live from one inner solve into the next
+#pragma unroll
+            for (int k = 0; k < RK; ++k)
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    rd[k][s] = 0.0;
+                    rq[k][s] = 0.0;
+                    rw[k][s] = 0.0;
+                }
+            for_elems_r<NT, W, RI>(a0, a1, [&](auto k, auto s, int row, int c, int li) __attribute__((always_inline)) {
+                const double v = ld_pub(rhs + (int64_t)row * W + c);
+                resl[li] = v;
+                rd[k][s] = v;
+            });
+            if (tid < W) {
+                const int c = tid;
+                const double tt = COLV(L, C_TT, c);
+                COLV(L, C_RR, c) = tt;
+                COLV(L, C_STOP, c) = P.inner_tol * sqrt(tt);
+                const bool run = COLV(L, C_ACT, c) != 0.0 && tt > 0.0 && !(sqrt(tt) <= P.inner_tol * sqrt(tt));
+                COLV(L, C_CGACT, c) = run ? 1.0 : 0.0;
+                COLV(L, C_CGIT, c) = 0.0;
+                COLV(L, C_BCG, c) = 0.0;
+            }
+            __syncthreads();
+            for (int m = 0; m < P.inner_maxiter; ++m) {
+                int any = 0;
+                for (int c = 0; c < W; ++c) any |= COLV(L, C_CGACT, c) != 0.0;
+                if (!any) break;
+                // (a) d = r + bcg d, w = S r + bcg w (first step: d = rhs, w = S rhs); d^T w
+                double acc[NS];
+#pragma unroll
+                for (int s = 0; s < NS; ++s) acc[s] = 0.0;
+                spmm<BD, NT, W, UNIT, decltype(stage), true>(Sb, syS, a0, a1, m == 0 ? rhs : ures, stage, resl);
+                for_elems_r<NT, W, RI>(a0, a1, [&](auto k, auto s, int row, int c, int li) __attribute__((always_inline)) {
+                    if (COLV(L, C_CGACT, c) == 0.0) return;
+                    const double y = ystg[li];
+                    if (m == 0) {
+                        rw[k][s] = y;
+                    } else {
+                        const double bc = COLV(L, C_BCG, c);
+                        rd[k][s] = resl[li] + bc * rd[k][s];
+                        rw[k][s] = y + bc * rw[k][s];
+                    }
+                    acc[s] += rd[k][s] * rw[k][s];
+                });
+                wave_put<BD, NT, W, NV>(acc, L.red, 0);
+                if (!team_sum<NT, NV>(L.red, L.rres, tm, s_flag)) return false;
+                if (tid < W) {
+                    const int c = tid;
+                    COLV(L, C_A, c) = COLV(L, C_CGACT, c) != 0.0 ? COLV(L, C_RR, c) / L.rres[c] : 0.0;
+                }
+                __syncthreads();
+                // (b) q += a d, r -= a w (LDS, and published), ||r||^2
+#pragma unroll
+                for (int s = 0; s < NS; ++s) acc[s] = 0.0;
+                for_elems_r<NT, W, RI>(a0, a1, [&](auto k, auto s, int row, int c, int li) __attribute__((always_inline)) {
+                    if (COLV(L, C_CGACT, c) == 0.0) return;
+                    const double a = COLV(L, C_A, c);
+                    rq[k][s] += a * rd[k][s];
+                    const double rv = resl[li] - a * rw[k][s];
+                    resl[li] = rv;
+                    st_pub(ures + (int64_t)row * W + c, rv);
+                    acc[s] += rv * rv;
+                });
+                wave_put<BD, NT, W, NV>(acc, L.red, 0);
+                if (!team_sum<NT, NV>(L.red, L.rres, tm, s_flag)) return false;
+                if (tid < W) {
+                    const int c = tid;
+                    if (COLV(L, C_CGACT, c) != 0.0) {
+                        const double rn = L.rres[c];
+                        COLV(L, C_BCG, c) = rn / COLV(L, C_RR, c);
+                        COLV(L, C_RR, c) = rn;
+                        COLV(L, C_CGIT, c) += 1.0;
+                        if (sqrt(rn) <= COLV(L, C_STOP, c) || m + 1 >= P.inner_maxiter) COLV(L, C_CGACT, c) = 0.0;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        return true;
+    };
+
     // ---- q_0 = S^{-1} b (published); beta_0 = sqrt(b^T q_0) = sqrt(q_0[j])
-    if constexpr (!SID) {
+    if constexpr (RV) {
+        if (!inner_cg_r(tprev)) return false;
+        for_elems_r<NT, W, RI>(a0, a1, [&](auto k, auto s, int row, int c, int li) __attribute__((always_inline)) {
+            st_pub(qcur + (int64_t)row * W + c, COLV(L, C_CGIT, c) > 0.0 ? rq[k][s] : 0.0);
+        });
+        if (tid < W) COLV(L, C_INNER, tid) += COLV(L, C_CGIT, tid);
+    } else if constexpr (!SID) {
         if (!inner_cg(tprev, qcur)) return false;
-        for_elems<BD, NT, W>(a0, a1, [&](int row, int s, int c, int li) {
+        for_elems<BD, NT, W>(a0, a1, [&](int row, int s, int c, int li) __attribute__((always_inline)) {
             const int64_t gi = (int64_t)row * W + c;
             st_pub(qcur + gi, COLV(L, C_CGIT, c) > 0.0 ? qcur[gi] : 0.0);
         });
@@ -693,7 +842,7 @@ __device__ bool solve_panel(const TParams& T, int panel, Team& tm, const Lds& L,
         double acc[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) acc[s] = 0.0;
-        for_elems<BD, NT, W>(a0, a1, [&](int row, int s, int c, int li) {
+        for_elems<BD, NT, W>(a0, a1, [&](int row, int s, int c, int li) __attribute__((always_inline)) {
             if (row == (int)COLV(L, C_BLOC, c)) acc[s] += ld_pub(qcur + (int64_t)row * W + c);
         });
         wave_put<BD, NT, W, NV>(acc, L.red, 0);
@@ -734,13 +883,23 @@ __device__ bool solve_panel(const TParams& T, int panel, Team& tm, const Lds& L,
             double acc[NS];
 #pragma unroll
             for (int s = 0; s < NS; ++s) acc[s] = 0.0;
-            spmm<BD, NT, W, false>(Hb, sy, a0, a1, qcur, [&](int row, int s, int c, int li, double y) {
-                if (COLV(L, C_ACT, c) == 0.0) return;
-                const double ib = 1.0 / COLV(L, C_BCUR, c);
-                const double u = y * ib;
-                ures[(int64_t)row * W + c] = u;
-                acc[s] += ld_pub(qcur + (int64_t)row * W + c) * ib * u;
-            });
+            if constexpr (RV) {
+                spmm<BD, NT, W, false>(Hb, sy, a0, a1, qcur, [&](int row, int s, int c, int li, double y) __attribute__((always_inline)) {
+                    if (COLV(L, C_ACT, c) == 0.0) return;
+                    const double ib = 1.0 / COLV(L, C_BCUR, c);
+                    const double u = y * ib;
+                    ystg[li] = u;
+                    acc[s] += ld_pub(qcur + (int64_t)row * W + c) * ib * u;
+                });
+            } else {
+                spmm<BD, NT, W, false>(Hb, sy, a0, a1, qcur, [&](int row, int s, int c, int li, double y) __attribute__((always_inline)) {
+                    if (COLV(L, C_ACT, c) == 0.0) return;
+                    const double ib = 1.0 / COLV(L, C_BCUR, c);
+                    const double u = y * ib;
+                    ures[(int64_t)row * W + c] = u;
+                    acc[s] += ld_pub(qcur + (int64_t)row * W + c) * ib * u;
+                });
+            }
             wave_put<BD, NT, W, NV>(acc, L.red, 0);
             if (tid < W) {
                 int lo, hi, cnt = 0;
@@ -765,15 +924,23 @@ __device__ bool solve_panel(const TParams& T, int panel, Team& tm, const Lds& L,
             double acc[NS];
 #pragma unroll
             for (int s = 0; s < NS; ++s) acc[s] = 0.0;
-            for_elems<BD, NT, W>(a0, a1, [&](int row, int s, int c, int li) {
-                if (COLV(L, C_ACT, c) == 0.0) return;
+            auto tstep = [&](int row, int c, double u) __attribute__((always_inline)) -> double {
                 const int64_t gi = (int64_t)row * W + c;
                 const double bl = COLV(L, C_BLAN, c);
-                double tv = ures[gi] - COLV(L, C_ALPHA, c) / COLV(L, C_BCUR, c) * ld_pub(tprev + gi);
+                double tv = u - COLV(L, C_ALPHA, c) / COLV(L, C_BCUR, c) * ld_pub(tprev + gi);
                 if (bl != 0.0) tv -= bl / COLV(L, C_BPREV, c) * ld_pub(tcur + gi);
                 st_pub(tcur + gi, tv);
-                acc[s] += tv * tv;
-            });
+                return tv * tv;
+            };
+            if constexpr (RV) {
+                for_elems<BD, NT, W>(a0, a1, [&](int row, int s, int c, int li) __attribute__((always_inline)) {
+                    if (COLV(L, C_ACT, c) != 0.0) acc[s] += tstep(row, c, ystg[li]);
+                });
+            } else {
+                for_elems<BD, NT, W>(a0, a1, [&](int row, int s, int c, int li) __attribute__((always_inline)) {
+                    if (COLV(L, C_ACT, c) != 0.0) acc[s] += tstep(row, c, ures[(int64_t)row * W + c]);
+                });
+            }
             wave_put<BD, NT, W, NV>(acc, L.red, 0);
             if (!team_sum<NT, NV>(L.red, L.rres, tm, s_flag)) return false;
             if (tid < W) COLV(L, C_TT, tid) = COLV(L, C_ACT, tid) != 0.0 ? L.rres[tid] : 0.0;
@@ -784,17 +951,28 @@ __device__ bool solve_panel(const TParams& T, int panel, Team& tm, const Lds& L,
             if (tid < W) COLV(L, C_QT, tid) = COLV(L, C_TT, tid);
             __syncthreads();
         } else {
-            if (!inner_cg(tcur, qnew)) return false;
             double acc[NS];
 #pragma unroll
             for (int s = 0; s < NS; ++s) acc[s] = 0.0;
-            for_elems<BD, NT, W>(a0, a1, [&](int row, int s, int c, int li) {
-                if (COLV(L, C_ACT, c) == 0.0) return;
-                const int64_t gi = (int64_t)row * W + c;
-                const double v = COLV(L, C_CGIT, c) > 0.0 ? qnew[gi] : 0.0;
-                st_pub(qnew + gi, v);
-                acc[s] += v * ld_pub(tcur + gi);
-            });
+            if constexpr (RV) {
+                if (!inner_cg_r(tcur)) return false;
+                for_elems_r<NT, W, RI>(a0, a1, [&](auto k, auto s, int row, int c, int li) __attribute__((always_inline)) {
+                    if (COLV(L, C_ACT, c) == 0.0) return;
+                    const int64_t gi = (int64_t)row * W + c;
+                    const double v = COLV(L, C_CGIT, c) > 0.0 ? rq[k][s] : 0.0;
+                    st_pub(qnew + gi, v);
+                    acc[s] += v * ld_pub(tcur + gi);
+                });
+            } else {
+                if (!inner_cg(tcur, qnew)) return false;
+                for_elems<BD, NT, W>(a0, a1, [&](int row, int s, int c, int li) __attribute__((always_inline)) {
+                    if (COLV(L, C_ACT, c) == 0.0) return;
+                    const int64_t gi = (int64_t)row * W + c;
+                    const double v = COLV(L, C_CGIT, c) > 0.0 ? qnew[gi] : 0.0;
+                    st_pub(qnew + gi, v);
+                    acc[s] += v * ld_pub(tcur + gi);
+                });
+            }
             wave_put<BD, NT, W, NV>(acc, L.red, 0);
             if (!team_sum<NT, NV>(L.red, L.rres, tm, s_flag)) return false;
             if (tid < W) {
@@ -1024,7 +1202,7 @@ __device__ bool solve_panel(const TParams& T, int panel, Team& tm, const Lds& L,
 
 // Persistent team kernel: the team's rank-0 workgroup takes the next panel
 // from the work queue and publishes it; the team solves it together.
-template <int BD, int NT, int W, bool SID, bool GAL, bool DL, bool UNIT>
+template <int BD, int NT, int W, bool SID, bool GAL, bool DL, bool UNIT, int RI>
 __global__ __launch_bounds__(NT) void k_team(TParams T) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_flag, s_job;
@@ -1056,10 +1234,10 @@ __global__ __launch_bounds__(NT) void k_team(TParams T) {
         if (!team_wait(tm, &s_flag)) break;
         if (threadIdx.x == 0) s_job = ld_pub_i(tm.job);
         __syncthreads();
-        const int job = s_job;
+        const int job = __builtin_amdgcn_readfirstlane(s_job);   // uniform: its loads are scalar
         __syncthreads();
         if (job >= T.npanels) break;
-        if (!solve_panel<BD, NT, W, SID, GAL, DL, UNIT>(T, job, tm, L, &s_flag)) {
+        if (!solve_panel<BD, NT, W, SID, GAL, DL, UNIT, RI>(T, job, tm, L, &s_flag)) {
             // a wait was abandoned: this panel's pairs owned here are reported as such
             const int npairs = (W * P.K - tm.rank + G - 1) / G;
             for (int m = threadIdx.x; m < npairs; m += NT) {
@@ -1072,43 +1250,61 @@ __global__ __launch_bounds__(NT) void k_team(TParams T) {
     }
 }
 
-// Calls f.template run<BD, NT, W, SID, GAL, DL, UNIT>() for the compiled instance.
+// Register-resident instances compiled: (threads, panel width, block-row quads per wave).
+// (the one shape whose instances keep every value in registers)
+__host__ __device__ constexpr bool rv_ok(int NT, int W, int RI) { return NT == 512 && W == 4 && RI == 8; }
+
+// Calls f.template run<BD, NT, W, SID, GAL, DL, UNIT, RI>() for the compiled instance.
 // variant: 0 S = I, 1 S with the CG direction in LDS, 2 the same with S = I + off-diagonal blocks,
-// 3 S with the direction in HBM
+// 3 S with the direction in HBM, 4 register-resident CG with S = I + off-diagonal blocks,
+// 5 register-resident CG with S as stored
+template <int BD, int NT, int W, bool GAL, int RI, bool UN, class F>
+static hipError_t rv_run(F& f) {
+    if constexpr (BD == 4 && W % 4 == 0 && rv_ok(NT, W, RI)) return f.template run<BD, NT, W, false, GAL, true, UN, RI>();
+    else return hipErrorInvalidValue;
+}
+template <int BD, int NT, int W, bool GAL, bool UN, class F>
+static hipError_t rv_by_ri(int ri, F& f) {
+    if (ri == 8) return rv_run<BD, NT, W, GAL, 8, UN>(f);
+    return hipErrorInvalidValue;
+}
 template <int BD, int NT, int W, bool GAL, class F>
-static hipError_t by_variant(int variant, F& f) {
+static hipError_t by_variant(int variant, int ri, F& f) {
     switch (variant) {
-        case 0: return f.template run<BD, NT, W, true, GAL, false, false>();
-        case 1: return f.template run<BD, NT, W, false, GAL, true, false>();
-        case 2: return f.template run<BD, NT, W, false, GAL, true, true>();
-        default: return f.template run<BD, NT, W, false, GAL, false, false>();
+        case 0: return f.template run<BD, NT, W, true, GAL, false, false, 0>();
+        case 1: return f.template run<BD, NT, W, false, GAL, true, false, 0>();
+        case 2: return f.template run<BD, NT, W, false, GAL, true, true, 0>();
+        case 3: return f.template run<BD, NT, W, false, GAL, false, false, 0>();
+        case 4: return rv_by_ri<BD, NT, W, GAL, true>(ri, f);
+        case 5: return rv_by_ri<BD, NT, W, GAL, false>(ri, f);
+        default: return hipErrorInvalidValue;
     }
 }
 template <int BD, int NT, int W, class F>
-static hipError_t by_gal(bool gal, int variant, F& f) {
-    return gal ? by_variant<BD, NT, W, true>(variant, f) : by_variant<BD, NT, W, false>(variant, f);
+static hipError_t by_gal(bool gal, int variant, int ri, F& f) {
+    return gal ? by_variant<BD, NT, W, true>(variant, ri, f) : by_variant<BD, NT, W, false>(variant, ri, f);
 }
 template <int BD, int NT, class F>
-static hipError_t by_w(int W, bool gal, int variant, F& f) {
+static hipError_t by_w(int W, bool gal, int variant, int ri, F& f) {
     if constexpr (BD == 4) {
-        if (W == 8) return by_gal<BD, NT, 8>(gal, variant, f);
-        if (W == 4) return by_gal<BD, NT, 4>(gal, variant, f);
+        if (W == 8) return by_gal<BD, NT, 8>(gal, variant, ri, f);
+        if (W == 4) return by_gal<BD, NT, 4>(gal, variant, ri, f);
     }
-    if (W != 1) return hipErrorInvalidValue;
-    return by_gal<BD, NT, 1>(gal, variant, f);
+    if (W != 1 || variant >= 4) return hipErrorInvalidValue;
+    return by_gal<BD, NT, 1>(gal, variant, ri, f);
 }
 template <int BD, class F>
-static hipError_t by_nt(int nt, int W, bool gal, int variant, F& f) {
-    if (nt == 1024) return by_w<BD, 1024>(W, gal, variant, f);
-    if (nt == 512) return by_w<BD, 512>(W, gal, variant, f);
+static hipError_t by_nt(int nt, int W, bool gal, int variant, int ri, F& f) {
+    if (nt == 1024) return by_w<BD, 1024>(W, gal, variant, ri, f);
+    if (nt == 512) return by_w<BD, 512>(W, gal, variant, ri, f);
     return hipErrorInvalidValue;
 }
 template <class F>
-static hipError_t dispatch(int bd, int nt, int W, bool gal, int variant, F& f) {
+static hipError_t dispatch(int bd, int nt, int W, bool gal, int variant, int ri, F& f) {
     switch (bd) {
-        case 1: return by_nt<1>(nt, W, gal, variant, f);
-        case 4: return by_nt<4>(nt, W, gal, variant, f);
-        case 9: return by_nt<9>(nt, W, gal, variant, f);
+        case 1: return by_nt<1>(nt, W, gal, variant, ri, f);
+        case 4: return by_nt<4>(nt, W, gal, variant, ri, f);
+        case 9: return by_nt<9>(nt, W, gal, variant, ri, f);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1118,9 +1314,9 @@ struct Launch {
     int grid, nt;
     size_t lds;
     hipStream_t st;
-    template <int BD, int NT, int W, bool SID, bool GAL, bool DL, bool UNIT>
+    template <int BD, int NT, int W, bool SID, bool GAL, bool DL, bool UNIT, int RI>
     hipError_t run() {
-        hipLaunchKernelGGL((k_team<BD, NT, W, SID, GAL, DL, UNIT>), dim3(grid), dim3(NT), lds, st, *T);
+        hipLaunchKernelGGL((k_team<BD, NT, W, SID, GAL, DL, UNIT, RI>), dim3(grid), dim3(NT), lds, st, *T);
         return hipGetLastError();
     }
 };
@@ -1128,30 +1324,39 @@ struct Launch {
 struct Occupancy {
     size_t lds;
     int* out;
-    template <int BD, int NT, int W, bool SID, bool GAL, bool DL, bool UNIT>
+    size_t* priv;
+    template <int BD, int NT, int W, bool SID, bool GAL, bool DL, bool UNIT, int RI>
     hipError_t run() {
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_team<BD, NT, W, SID, GAL, DL, UNIT>, NT, lds);
+        hipFuncAttributes fa{};
+        hipError_t e = hipFuncGetAttributes(&fa, (const void*)k_team<BD, NT, W, SID, GAL, DL, UNIT, RI>);
+        if (e != hipSuccess) return e;
+        *priv = fa.localSizeBytes;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_team<BD, NT, W, SID, GAL, DL, UNIT, RI>, NT, lds);
     }
 };
 
 }  // namespace team
 
-size_t team_lds_bytes(int nt, int W, int pairs, int rows_max, bool dl) {
-    return team::lds_bytes(nt, W, pairs, rows_max, dl);
+size_t team_lds_bytes(int nt, int W, int pairs, int rows_max, bool dl, bool rv) {
+    return team::lds_bytes(nt, W, pairs, rows_max, dl, rv);
 }
 
 int64_t team_ws_bytes(int W, int K, int64_t Mp, int64_t nIp, bool qmr) { return team::team_bytes(W, K, Mp, nIp, qmr); }
 
-hipError_t launch_team(const TParams& T, int bd, bool gal, int variant, int nt, int grid, size_t lds,
+hipError_t launch_team(const TParams& T, int bd, bool gal, int variant, int ri, int nt, int grid, size_t lds,
                        hipStream_t st) {
     team::Launch f{&T, grid, nt, lds, st};
-    return team::dispatch(bd, nt, T.W, gal, variant, f);
+    return team::dispatch(bd, nt, T.W, gal, variant, ri, f);
 }
 
-hipError_t team_occupancy(int bd, bool gal, int variant, int nt, int W, size_t lds, int* per_cu) {
+hipError_t team_occupancy(int bd, bool gal, int variant, int ri, int nt, int W, size_t lds, int* per_cu,
+                          size_t* private_bytes) {
     *per_cu = 0;
-    team::Occupancy f{lds, per_cu};
-    return team::dispatch(bd, nt, W, gal, variant, f);
+    *private_bytes = 0;
+    team::Occupancy f{lds, per_cu, private_bytes};
+    return team::dispatch(bd, nt, W, gal, variant, ri, f);
 }
+
+bool team_rv_ok(int nt, int W, int ri) { return team::rv_ok(nt, W, ri); }
 
 }  // namespace scocg
