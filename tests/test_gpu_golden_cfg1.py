@@ -1,0 +1,92 @@
+"""The benchmarked launch shape on configuration 1's matrices against the
+oracle itself: the stored oracle results of tests/golden/cfg1_lanczos_G.txt
+(written by tests/golden/make_cfg1_lanczos.py from oracle.scocg_lanczos at tol
+1e-10: the first four RHS, eight shifts spread over the 128-point mesh, every
+requested row).  The GPU runs the same tolerance with the one-workgroup
+Lanczos-basis kernel in the instance the benchmark times (1024 threads, the
+inner CG's direction in LDS, S applied as I plus its off-diagonal blocks), and
+with the team solver on panels of the same RHS.  Rule: per (RHS, shift)
+||G_gpu - G_oracle|| / ||G_oracle|| <= 1e-8 over the requested rows, equal
+status, iteration counts within 25%; a pair outside 1e-8 whose count differs
+must lie, like the oracle's, within the a-priori bound of the exact solution
+(sparse LU of z_k S - H)."""
+import os
+
+import numpy as np
+import pytest
+
+from synth import bsr_to_scipy, make_config
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _load():
+    rows = np.loadtxt(os.path.join(HERE, "golden", "cfg1_lanczos_G.txt"))
+    ks = np.unique(rows[:, 2].astype(int))
+    nrhs = int(rows[:, 0].max()) + 1
+    ref = {}
+    for r in rows:
+        j, i, k = int(r[0]), int(r[1]), int(r[2])
+        ref.setdefault((j, k), {"G": {}, "iters": int(r[7]), "status": int(r[8])})["G"][i] = r[5] + 1j * r[6]
+    return ks, nrhs, ref
+
+
+@pytest.fixture(scope="module")
+def setup(gpu_lib):
+    from paper_1402_7285_amd import binding as B
+    ks, nrhs, ref = _load()
+    prob = make_config(1, nrhs=nrhs)
+    return B, prob, ks, ref
+
+
+def _check(B, prob, ks, ref, r, tag):
+    from scipy.sparse.linalg import eigsh, splu
+    H, S = bsr_to_scipy(prob.H), bsr_to_scipy(prob.S)
+    lam_min = float(eigsh(S, k=1, which="SA", return_eigenvectors=False)[0])
+    assert lam_min > 0.1
+    worst, moved = 0.0, 0
+    for j in range(prob.nrhs):
+        rows = prob.outs(j)
+        for a, k in enumerate(ks):
+            e = ref[(j, int(k))]
+            g_or = np.array([e["G"][int(i)] for i in rows])
+            g_gpu = r["G"][j][a]
+            assert r["status"][j][a] == e["status"], (tag, j, k)
+            d = abs(int(r["iters"][j][a]) - e["iters"])
+            assert d <= 0.25 * e["iters"], (tag, j, k, r["iters"][j][a], e["iters"])
+            rel = np.linalg.norm(g_gpu - g_or) / np.linalg.norm(g_or)
+            worst = max(worst, rel)
+            if rel <= 1e-8:
+                continue
+            assert d > 0, (tag, j, k, rel)
+            moved += 1
+            z = prob.shifts[k]
+            b = np.zeros(prob.M, dtype=np.complex128)
+            b[prob.rhs[j]] = 1.0
+            xs = splu((z * S - H).tocsc().astype(np.complex128)).solve(b)[rows]
+            bound = 2 * 1e-10 / (abs(z.imag) * lam_min)       # ||A^-1|| <= 1/(|Im z| lambda_min(S)), residual 2 tol
+            assert np.linalg.norm(g_gpu - xs) <= bound and np.linalg.norm(g_or - xs) <= bound, (tag, j, k)
+    print(f"[cfg1 golden] {tag}: worst rel err {worst:.2e} vs the oracle; pairs judged by the bound {moved}",
+          flush=True)
+
+
+def test_benchmark_instance_against_stored_oracle(setup):
+    B, prob, ks, ref = setup
+    P = B.Problem(prob.H, prob.S)
+    plan = B.Plan(P, prob.shifts[ks], prob.rhs, method=B.METHOD_COCG_LANCZOS, tol=1e-10, team_size=-1, threads=1024,
+                  out_ptr=prob.out_ptr, out_rows=prob.out_rows)
+    info = plan.info
+    assert info["threads"] == 1024 and not info["global"] & 64, info        # one workgroup per RHS, 1024 threads
+    assert info["global"] & 16 and info["global"] & 32, info                 # direction in LDS, S = I + off-diagonal
+    _check(B, prob, ks, ref, plan.solve(), "one workgroup, 1024 threads")
+
+
+def test_team_solver_against_stored_oracle(setup):
+    B, prob, ks, ref = setup
+    P = B.Problem(prob.H, prob.S)
+    plan = B.Plan(P, prob.shifts[ks], prob.rhs, method=B.METHOD_COCG_LANCZOS, tol=1e-10, team_size=8, panel_width=4,
+                  out_ptr=prob.out_ptr, out_rows=prob.out_rows)
+    assert plan.info["global"] & 64 and plan.info["global"] & 128, plan.info   # team, matrix cores
+    _check(B, prob, ks, ref, plan.solve(), "team of 8, panel of 4")

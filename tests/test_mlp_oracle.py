@@ -72,6 +72,7 @@ def test_features_against_dense_definitions():
     p = make_problem(lattice="fcc", L=4, bdim=9, hop=(0.0, 0.5), s_scale=0.03, K=4, nrhs=6, radius=(1.2, 1.6),
                      seed_key=(5, 6, 7))
     Hd = bsr_to_dense(p.H)
+    Sd = bsr_to_dense(p.S)
     for j in range(p.nrhs):
         f = F.rhs_features(p, j)
         atoms = p.cluster(j)
@@ -88,6 +89,16 @@ def test_features_against_dense_definitions():
         Hcc = Hd[c * 9:(c + 1) * 9, c * 9:(c + 1) * 9]
         ev = np.linalg.eigvalsh(Hcc)
         assert f[9] <= ev[0] + 1e-12 and ev[-1] <= f[10] + 1e-12       # Gershgorin encloses the spectrum
+        # features 1, 3 and 15 from the dense matrices: nonzero 9x9 blocks of the cluster's principal
+        # submatrix per atom; nonzero blocks in the cluster rows of c's neighbours; mean ||S_cb||_F over them
+        def blk(A, a, b):
+            return A[a * 9:(a + 1) * 9, b * 9:(b + 1) * 9]
+        nzb = np.array([[np.any(blk(Hd, a, b) != 0) for b in atoms] for a in atoms])
+        assert np.isclose(f[1], nzb.sum() / atoms.size)
+        ci = int(np.searchsorted(atoms, c))
+        nbrs = [i for i in range(atoms.size) if i != ci and nzb[ci, i]]
+        assert f[3] == sum(int(nzb[i].sum()) for i in nbrs)
+        assert np.isclose(f[15], np.mean([np.linalg.norm(blk(Sd, c, int(atoms[i]))) for i in nbrs]))
     # no hopping: neighbour block norms vanish
     q = make_problem(lattice="fcc", L=3, bdim=9, hop=(0.0, 0.0), K=4, nrhs=2, radius=(1.0, 1.2), seed_key=(1, 1, 1))
     fq = F.rhs_features(q, 0)
