@@ -298,19 +298,19 @@ def chunked(B, P, prob, kw, args):
     so that each launch holds RHS of similar cost; the rate is the total of
     converged pairs over the total time."""
     import torch
-    from paper_1402_7285_amd import binning
     ent = np.diff(prob.cluster_ptr).astype(np.float64) if prob.cluster_ptr is not None else np.ones(prob.nrhs)
-    order = binning.order_longest_first(ent) if args.chunk_order == "size" else np.arange(prob.nrhs)
+    order = longest_first(ent) if args.chunk_order == "size" else np.arange(prob.nrhs)
     stream = torch.cuda.current_stream()
-    total_s, good, pairs, outer = 0.0, 0, 0, []
+    total_s, total_alg, good, pairs, outer = 0.0, 0.0, 0, 0, []
     launches = []
     for c0 in range(0, prob.nrhs, args.chunk):
         sub = prob.subset(order[c0:c0 + args.chunk])
         skw = dict(out_ptr=sub.out_ptr, out_rows=sub.out_rows)
         if sub.cluster_ptr is not None:
             skw.update(cluster_ptr=sub.cluster_ptr, cluster_atoms=sub.cluster_atoms)
+        team = dict(team_size=args.team, panel_width=args.panel) if args.method != "cocg" else {}
         plan = B.Plan(P, sub.shifts, sub.rhs, tol=args.tol, threads=args.threads, slots=args.slots,
-                      method=METHODS[args.method], **skw)
+                      method=METHODS[args.method], **team, **skw)
         bufs = plan.alloc_outputs()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -322,34 +322,57 @@ def chunked(B, P, prob, kw, args):
         st, rs = bufs["status"].cpu().numpy(), bufs["resid"].cpu().numpy()
         g = int(np.sum((st == 0) & (rs <= 1e-6)))
         stats = plan.stats()
+        qmr = bool(plan.info["global"] & 4)
+        gal = bool(plan.info["global"] & 8)
+        nout = np.diff(sub.out_ptr)
+        if qmr:
+            alg = algorithmic_bytes_qmr(stats, nout, sub.bdim, sub.S is not None, 1, gal)
+        else:
+            alg = algorithmic_bytes(stats, nout, sub.nshift, sub.bdim, sub.S is not None, PREC[args.precision],
+                                    bool(plan.info["global"] & 2), 1, True)
         total_s += sec
+        total_alg += alg
         good += g
         pairs += st.size
         outer.append(stats[:, 0])
         launches.append({"rhs": sub.nrhs, "seconds": sec, "max_M": int(stats[:, 4].max()),
-                         "outer_max": int(stats[:, 0].max())})
+                         "outer_max": int(stats[:, 0].max()), "team_size": plan.info["team_size"],
+                         "threads": plan.info["threads"], "workgroups": plan.info["slots"],
+                         "algorithmic_GBps": alg / sec / 1e9})
         print(f"[bench] launch {len(launches)}: {sub.nrhs} RHS, {sec:.1f} s, converged {g}/{st.size}, "
-              f"largest cluster M={int(stats[:, 4].max())}", file=sys.stderr, flush=True)
+              f"largest cluster M={int(stats[:, 4].max())}, team {plan.info['team_size']}, "
+              f"{alg / sec / 1e9:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
         del plan, bufs
     outer = np.concatenate(outer)
+    ach = total_alg / total_s / 1e9
     out = {"metric": METRIC, "value": good / total_s, "unit": "solves/s", "n_gpus": 1, "seconds": total_s,
            "converged_pairs": good, "pairs": pairs, "launches": launches,
+           "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": ach / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": total_alg},
            "outer_iterations": {"mean": float(outer.mean()), "max": int(outer.max())},
            "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]['desc']}", "nrhs": prob.nrhs,
                       "chunk": args.chunk, "order": args.chunk_order, "method": args.method,
+                      "sample": (f"the first {prob.nrhs} RHS of the workload in generation order (a random sample: "
+                                 f"RHS orbitals and cluster radii are independent draws)"
+                                 if args.nrhs else "every RHS"),
                       "form": "persistent launches of chunk RHS each, in order of decreasing cluster size"}}
     print(json.dumps(out), flush=True)
+
+
+def longest_first(cost):
+    """Queue order by decreasing cost (stable for ties)."""
+    return np.argsort(-np.asarray(cost, dtype=np.float64), kind="stable").astype(np.int32)
 
 
 def binning_ab(B, args):
     """Learned binning, measured: solve the training workload and log each
     RHS's outer-iteration count, train the cost network on the GPU on those
-    counts, then time the test workload (args.workload) with the work queue
-    in index order, by local-pattern size, by the learned cost and by the
-    true cost (known from the index-order solve).  Results must be identical
-    in every order; only the time changes."""
+    counts (scocg_mlp_train), then time the test workload (args.workload)
+    with the work queue in index order, by local-pattern size and by the
+    learned cost (both set by scocg_schedule), and by the true cost (known
+    from the index-order solve).  Results must be identical in every order;
+    only the time changes."""
     import torch
-    from paper_1402_7285_amd import binning
     from synth import make_config, mlp_init_weights, rngs_for
 
     def setup(name, nrhs=None):
@@ -361,9 +384,13 @@ def binning_ab(B, args):
             kw.update(cluster_ptr=prob.cluster_ptr, cluster_atoms=prob.cluster_atoms)
         return prob, P, kw
 
-    def timed(P, prob, kw, order=None):
+    team = dict(team_size=args.team, panel_width=args.panel) if args.method != "cocg" else {}
+
+    def timed(P, prob, kw, order=None, model=None, schedule=False):
         plan = B.Plan(P, prob.shifts, prob.rhs, tol=args.tol, threads=args.threads, slots=args.slots,
-                      order=order, method=METHODS[args.method], **kw)
+                      order=order, method=METHODS[args.method], **team, **kw)
+        if schedule:
+            plan.schedule(model)
         bufs = plan.alloc_outputs()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -381,10 +408,10 @@ def binning_ab(B, args):
     print(f"[binning] training solve {sec:.1f} s", file=sys.stderr, flush=True)
     rg = rngs_for((1402, 7285, 4))
     t0 = time.perf_counter()
-    model = binning.train(feats, np.log(st[:, 0].astype(np.float64)), mlp_init_weights(rg["mlp_init"]),
-                          rg["mlp_shuffle"], epochs=args.binning_epochs, batch=256, lr=3e-3)
+    model, best_val = B.scocg_mlp_train(feats, np.log(st[:, 0].astype(np.float64)),
+                                        init_weights=mlp_init_weights(rg["mlp_init"]), seed=1402_7285_4,
+                                        epochs=args.binning_epochs, batch=256, lr=3e-3)
     t_train = time.perf_counter() - t0
-    best_val = float(min(h[2] for h in model.history))
     print(f"[binning] trained in {t_train:.1f} s, best validation MSE {best_val:.3f}", file=sys.stderr, flush=True)
     del plan, bufs, Ptr
     torch.cuda.empty_cache()
@@ -397,16 +424,15 @@ def binning_ab(B, args):
     print(f"[binning] test workload {args.workload}: {pte.nrhs} RHS, index order {sec_index:.1f} s",
           file=sys.stderr, flush=True)
     del bufs0
-    pred = binning.predict(model, ft)
+    pred = B.scocg_mlp_predict(model, ft).astype(np.float64)
     truth = st0[:, 0].astype(np.float64)
-    ent = binning.entries_per_rhs(ft)
+    ent = ft[:, 0].astype(np.float64) * ft[:, 1].astype(np.float64)
     corr = float(np.corrcoef(pred, np.log(truth))[0, 1])
-    orders = {"by_size": binning.order_longest_first(ent),
-              "learned": binning.order_longest_first(np.exp(pred) * ent),
-              "true_cost": binning.order_longest_first(truth * ent)}
+    runs = {"by_size": dict(schedule=True), "learned": dict(schedule=True, model=model),
+            "true_cost": dict(order=longest_first(truth * ent))}
     times = {"index": sec_index}
-    for name, order in orders.items():
-        _, b, sec = timed(Pte, pte, kwte, order=order)
+    for name, how in runs.items():
+        _, b, sec = timed(Pte, pte, kwte, **how)
         same = bool(torch.equal(b["out"].cpu(), ref))
         times[name] = sec
         print(f"[binning] {name} order {sec:.1f} s, results identical: {same}", file=sys.stderr, flush=True)
@@ -420,7 +446,8 @@ def binning_ab(B, args):
            "gain_learned_vs_index": times["index"] / times["learned"],
            "gain_learned_vs_by_size": times["by_size"] / times["learned"],
            "pred_corr_log_iters": corr, "best_val_mse": best_val, "train_seconds": t_train,
-           "slots": plan0.info["slots"], "threads": plan0.info["threads"], "method": args.method}
+           "slots": plan0.info["slots"], "threads": plan0.info["threads"], "method": args.method,
+           "team_size": plan0.info["team_size"], "panel_width": plan0.info["panel_width"]}
     print(json.dumps(out), flush=True)
 
 

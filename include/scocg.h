@@ -152,10 +152,12 @@ typedef struct {
     int32_t maxiter;        /* outer iterations; 0 = max(1000, 4*M_j) */
     int32_t precision;      /* SCOCG_FP64 / SCOCG_FP32 / SCOCG_FP32_BF16 */
     int32_t replace_every;  /* FP32 forms: FP64 residual replacement of the seed every
-                               this many iterations; 0 = off (default: replacing the
-                               seed residual breaks the collinearity the shifted
-                               recurrences rely on once the FP32 gap is not small
-                               against the residual, so it is opt-in) */
+                               this many iterations; 0 = off (default).  A replacement is
+                               taken only while the gap between the true and the recursive
+                               residual is at most 0.1 of the latter (a seed taken over by a
+                               switch can carry a larger gap, and replacing it would break
+                               the recurrences).  It reaches the seeds only: the other
+                               shifts keep their FP32 gap, which the audit and fallback fix */
     int32_t inner_maxiter;  /* inner CG iteration cap */
     double  inner_tol;      /* inner CG stop: ||res|| <= inner_tol * ||rho|| (FP64) */
     double  inner_tol_lo;   /* same for the FP32 inner CG */
@@ -409,6 +411,34 @@ scocg_status scocg_mlp_train(const float* feats, const float* log_iters, int64_t
  * pointer, n < 0, a standard deviation <= 0 in the model), E_NOMEM, E_DEVICE.
  */
 scocg_status scocg_mlp_predict(const float* model, const float* feats, int64_t n, float* pred);
+
+/*
+ * Replace the work-queue order of a plan (the permutation the plan was
+ * created with, or index order): order is a host permutation of
+ * 0..nrhs-1, NULL = index order.  The order changes timing only, never
+ * results: each RHS's solve does not depend on when it runs.  With panels
+ * of several RHS (panel_width > 1) the RHS that share a panel are the
+ * consecutive entries of the order.  Synchronous (waits for the device,
+ * so no launch of the plan still reads the old order; a captured graph
+ * keeps working and sees the new order).  Errors: E_ARG (NULL plan, not a
+ * permutation), E_DEVICE.
+ */
+scocg_status scocg_plan_set_order(scocg_plan* plan, const int32_t* order);
+
+/*
+ * Learned binning (the queue order of the persistent launch): computes the
+ * 16 features of every RHS (scocg_features), predicts its log outer
+ * iterations with a scocg_mlp_train model, takes as its cost the predicted
+ * iterations times the block entries of its local pattern (features 0 x 1),
+ * and sets the plan's order to decreasing cost (stable: ties keep index
+ * order), so long solves start first and panels (panel_width > 1) group
+ * RHS of similar predicted cost, which wait less for each other.  model
+ * NULL: cost = block entries (by-size order).  order_out (host int32
+ * [nrhs]) and cost_out (host float[nrhs]) may be NULL.  Synchronous.
+ * Errors: E_ARG (NULL plan, a bad model, a non-finite cost), E_NOMEM,
+ * E_DEVICE.
+ */
+scocg_status scocg_schedule(scocg_plan* plan, const float* model, int32_t* order_out, float* cost_out);
 
 /* Energy integration of G (the density of states and the density matrix,
  * Sec. 2-3: the Green's function as the analysis object).  G is the output

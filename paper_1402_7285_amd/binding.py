@@ -35,6 +35,7 @@ EXPORTS = (
     "scocg_mlp_train_step", "scocg_plan_integrate", "scocg_matrix_from_mtx", "scocg_matrix_shape",
     "scocg_matrix_export_bsr", "scocg_solve_device", "scocg_sync", "scocg_mlp_cfg_default",
     "scocg_mlp_model_floats", "scocg_mlp_train", "scocg_mlp_predict", "scocg_plan_cohp", "scocg_autotune_team",
+    "scocg_plan_set_order", "scocg_schedule",
 )
 
 
@@ -114,6 +115,8 @@ def _declare(lib):
         "scocg_mlp_model_floats": (i64, []),
         "scocg_mlp_train": (st, [_VP, _VP, i64, C.POINTER(scocg_mlp_cfg), _VP, C.POINTER(C.c_double)]),
         "scocg_mlp_predict": (st, [_VP, _VP, i64, _VP]),
+        "scocg_plan_set_order": (st, [_VP, _VP]),
+        "scocg_schedule": (st, [_VP, _VP, _VP, _VP]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -521,6 +524,26 @@ class Plan:
             stream = torch.cuda.current_stream()
         scocg_plan_cohp(self.h, rho, out, stream)
         return out[:rows]
+
+    def set_order(self, order=None):
+        """Replace the work-queue order (host permutation of 0..nrhs-1; None = index order)."""
+        o = None if order is None else np.ascontiguousarray(order, dtype=np.int32)
+        if o is not None and o.shape != (self.nrhs,):
+            raise ValueError("order must have nrhs entries")
+        _check(load().scocg_plan_set_order(self.h, None if o is None else _ptr(o)))
+
+    def schedule(self, model=None):
+        """Learned binning: order the queue by decreasing predicted cost (model from
+        scocg_mlp_train; None = by local-pattern size).  Returns (order, cost)."""
+        m = None
+        if model is not None:
+            m = np.ascontiguousarray(model, dtype=np.float32)
+            if m.size != scocg_mlp_model_floats():
+                raise ValueError("model size")
+        order = np.zeros(max(1, self.nrhs), dtype=np.int32)
+        cost = np.zeros(max(1, self.nrhs), dtype=np.float32)
+        _check(load().scocg_schedule(self.h, None if m is None else _ptr(m), _ptr(order), _ptr(cost)))
+        return order[: self.nrhs], cost[: self.nrhs]
 
     def features(self):
         """[nrhs, 16] FP32 features computed on the device (torch tensor)."""

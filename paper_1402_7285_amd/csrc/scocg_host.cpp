@@ -1757,3 +1757,58 @@ extern "C" scocg_status scocg_mlp_predict(const float* model, const float* feats
     HIP_TRY(hipMemcpy(pred, dy.p, sizeof(float) * n, hipMemcpyDeviceToHost));
     return SCOCG_OK;
 }
+
+// ---------------------------------------------------------------------------
+// work-queue order of a plan: set directly, or scheduled from predicted costs
+// ---------------------------------------------------------------------------
+extern "C" scocg_status scocg_plan_set_order(scocg_plan* pl, const int32_t* order) {
+    if (!pl) return fail(SCOCG_E_ARG, "plan is NULL");
+    const int32_t nrhs = pl->nrhs;
+    if (nrhs == 0) return SCOCG_OK;
+    std::vector<int32_t> o(nrhs);
+    if (order) {
+        std::vector<char> seen(nrhs, 0);
+        for (int32_t r = 0; r < nrhs; ++r) {
+            if (order[r] < 0 || order[r] >= nrhs || seen[order[r]]) return fail(SCOCG_E_ARG, "order is not a permutation");
+            seen[order[r]] = 1;
+            o[r] = order[r];
+        }
+    } else {
+        for (int32_t r = 0; r < nrhs; ++r) o[r] = r;
+    }
+    HIP_TRY(hipSetDevice(pl->P->device));
+    HIP_TRY(hipDeviceSynchronize());   // no launch of this plan may still read the old order
+    HIP_TRY(hipMemcpy(pl->dorder, o.data(), sizeof(int32_t) * (size_t)nrhs, hipMemcpyHostToDevice));
+    return SCOCG_OK;
+}
+
+extern "C" scocg_status scocg_schedule(scocg_plan* pl, const float* model, int32_t* order_out, float* cost_out) {
+    using namespace scocg;
+    if (!pl) return fail(SCOCG_E_ARG, "plan is NULL");
+    const int32_t nrhs = pl->nrhs;
+    if (nrhs == 0) return SCOCG_OK;
+    HIP_TRY(hipSetDevice(pl->P->device));
+    DevBuf df;
+    if (!df.alloc(sizeof(float) * (size_t)nrhs * NIN)) return fail(SCOCG_E_NOMEM, "feature buffer");
+    scocg_status st = scocg_features(pl, df.as<float>(), nullptr);
+    if (st < 0) return st;
+    HIP_TRY(hipDeviceSynchronize());
+    std::vector<float> F((size_t)nrhs * NIN), pred(nrhs, 0.f);
+    HIP_TRY(hipMemcpy(F.data(), df.p, sizeof(float) * F.size(), hipMemcpyDeviceToHost));
+    if (model && (st = scocg_mlp_predict(model, F.data(), nrhs, pred.data())) < 0) return st;
+    // cost = predicted outer iterations x block entries of the local pattern (features 0 and 1)
+    std::vector<double> cost(nrhs);
+    for (int32_t r = 0; r < nrhs; ++r) {
+        const double ent = (double)F[(size_t)r * NIN + 0] * (double)F[(size_t)r * NIN + 1];
+        cost[r] = (model ? std::exp((double)pred[r]) : 1.0) * ent;
+        if (!std::isfinite(cost[r])) return fail(SCOCG_E_ARG, "predicted cost of RHS %d is not finite", r);
+    }
+    std::vector<int32_t> o(nrhs);
+    for (int32_t r = 0; r < nrhs; ++r) o[r] = r;
+    std::stable_sort(o.begin(), o.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    if ((st = scocg_plan_set_order(pl, o.data())) < 0) return st;
+    if (order_out) std::memcpy(order_out, o.data(), sizeof(int32_t) * (size_t)nrhs);
+    if (cost_out)
+        for (int32_t r = 0; r < nrhs; ++r) cost_out[r] = (float)cost[r];
+    return SCOCG_OK;
+}

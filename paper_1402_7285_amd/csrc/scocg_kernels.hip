@@ -31,6 +31,9 @@ namespace scocg {
 
 enum { ST_CONVERGED = 0, ST_MAXITER = 1, ST_BREAKDOWN = 2, ST_NONFINITE = 3 };
 
+// Seed residual replacement is taken only while ||true - recursive|| <= 0.1 ||recursive||.
+constexpr double REPLACE_GAP2 = 1e-2;
+
 // A local system seen from one workgroup.
 struct Sys {
     const int64_t* rowptr;
@@ -683,22 +686,37 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L) {
                 const zc z2 = zmk(P.z[2 * s], P.z[2 * s + 1]);
                 const double nr2 = true_residual<BD, NT, SID>(P, sy, z2, xhi + (int64_t)s * Mp, q64, rho64,
                                                               ri.b_local, L.red);
-                double2* rr64 = SID ? rho64 : r64;
-                if constexpr (!SID) inner_total += inner_cg<BD, NT, double, double>(P.Sv64, sy, rho64, rr64, res64,
-                                                                                    d64, w64, nr2, P.inner_tol,
-                                                                                    P.inner_maxiter, L.red);
-                double g2[2] = {0.0, 0.0};
+                // Replacing the recursive residual keeps the recurrences valid only while the gap
+                // between it and the true residual is small against it.  A seed taken over by a
+                // switch carries the FP32 gap of its whole history as a shifted system, which can
+                // exceed its residual: replacing then destroys the seed's conjugacy and the
+                // iteration stalls until the shifted scalars overflow.  Such replacements are skipped.
+                double gd[2] = {0.0, 0.0};
                 for (int i = tid; i < M; i += NT) {
-                    const zc a = ld<double>(rho64, i), b = ld<double>(rr64, i);
-                    const zc t = zmul(a, b);
-                    g2[0] += t.re;
-                    g2[1] += t.im;
-                    st<TV>(rho, i, a);
-                    if constexpr (!SID) st<TV>(r, i, b);
+                    const zc a = ld<double>(rho64, i), c = ld<TV>(rho, i);
+                    const double dr = a.re - c.re, di = a.im - c.im;
+                    gd[0] += dr * dr + di * di;
+                    gd[1] += c.re * c.re + c.im * c.im;
                 }
-                block_sum<NT, 2>(g2, L.red);
-                gamma = zmk(g2[0], g2[1]);
-                ++nrepl;
+                block_sum<NT, 2>(gd, L.red);
+                if (gd[0] <= REPLACE_GAP2 * gd[1]) {
+                    double2* rr64 = SID ? rho64 : r64;
+                    if constexpr (!SID) inner_total += inner_cg<BD, NT, double, double>(P.Sv64, sy, rho64, rr64, res64,
+                                                                                        d64, w64, nr2, P.inner_tol,
+                                                                                        P.inner_maxiter, L.red);
+                    double g2[2] = {0.0, 0.0};
+                    for (int i = tid; i < M; i += NT) {
+                        const zc a = ld<double>(rho64, i), b = ld<double>(rr64, i);
+                        const zc t = zmul(a, b);
+                        g2[0] += t.re;
+                        g2[1] += t.im;
+                        st<TV>(rho, i, a);
+                        if constexpr (!SID) st<TV>(r, i, b);
+                    }
+                    block_sum<NT, 2>(g2, L.red);
+                    gamma = zmk(g2[0], g2[1]);
+                    ++nrepl;
+                }
             }
         }
         alpha_prev = alpha_n;

@@ -112,3 +112,73 @@ def test_cfg2_full_size_smallest_clusters(B, form):
     assert np.all(r["resid"] <= tol)
     every = list(range(0, prob.nshift, 8)) + [prob.nshift - 1]
     _check_sampled(prob, r, every, tol, label=f"cfg2 {form} FP64")
+
+
+def test_cfg2_full_size_largest_cluster_team(B):
+    """Configuration 2's largest cluster among its first 64 RHS (r = 4a class,
+    M_j = 9,495), solved by the team solver (the library's choice for
+    clusters this large: 8 workgroups split the cluster's rows), every 32nd
+    shift and the last against sparse LU of the local system.  One workgroup
+    alone needs over two minutes for this RHS; the team bounds the launch by
+    an eighth of that work plus its waits."""
+    full = make_config(2, nrhs=64)
+    sizes = np.diff(full.cluster_ptr)
+    prob = full.subset([int(np.argmax(sizes))])
+    tol = 1e-6
+    P, plan = _plan(B, prob, tol=tol, method=2)
+    assert plan.info["global"] & 64 and plan.info["team_size"] == 8, plan.info
+    r = plan.solve()
+    assert np.all(r["status"] == CONVERGED)
+    assert np.all(r["resid"] <= tol)
+    assert r["stats"][0][4] == 9 * int(sizes.max())
+    every = list(range(0, prob.nshift, 32)) + [prob.nshift - 1]
+    _check_sampled(prob, r, every, tol, label="cfg2 largest cluster, team of 8")
+    print(f"[fullsize] cfg2 largest cluster: {int(r['stats'][0][0])} outer iterations", flush=True)
+
+
+def test_cfg3_fp32_subset(B):
+    """Configuration 3: configuration 2's inputs at tol 1e-6 in the FP32 form
+    (FP32 blocks, complex FP32 vectors and updates, FP64 scalar recurrences,
+    FP64 seed residual replacement every 20 iterations, FP64 audit of every
+    pair and single-shift FP64 re-solve where the audit finds it above tol),
+    on the smallest cluster of the first 64 RHS (M_j = 1,269) and every 16th
+    of the 256 shifts, the whole x (the FP64 re-solves of the pairs the FP32
+    process leaves above tol cost minutes per RHS at all 256 shifts).
+    Reported: the maximum relative error of G_jj(z_k) and of x_j(z_k) against
+    the exact FP64 solution (sparse LU of z_k S - H on the cluster, the plain
+    definition of the result), before and after the audit; required: every
+    pair converged with audited residual <= tol, and every x within the
+    a-priori bound 2 tol / (|Im z| lam_min(S)) of the exact one."""
+    full = make_config(3, nrhs=64)
+    sizes = np.diff(full.cluster_ptr)
+    prob = full.subset(np.argsort(sizes, kind="stable")[:1])
+    shifts = prob.shifts[::16]
+    tol = 1e-6
+    P = B.Problem(prob.H, prob.S)
+    Hcsr, Scsr = bsr_to_scipy(prob.H), bsr_to_scipy(prob.S)
+    Hc, Sc, loc, orb = local_system(prob, 0, Hcsr, Scsr)
+    lam = _lam_min_lower(Sc)
+    b = np.zeros(orb.size, dtype=np.complex128)
+    b[loc] = 1.0
+    exact = [sla.splu((z * Sc - Hc).tocsc()).solve(b) for z in shifts]
+    res = {}
+    for audit in (0, 1):
+        plan = B.Plan(P, shifts, prob.rhs, full_x=True, cluster_ptr=prob.cluster_ptr,
+                      cluster_atoms=prob.cluster_atoms, tol=tol, precision=B.FP32, replace_every=20, method=0,
+                      audit=audit)
+        r = plan.solve()
+        st = r["stats"][0]
+        wx = max(np.linalg.norm(r["G"][0][k] - xs) / np.linalg.norm(xs) for k, xs in enumerate(exact))
+        wg = max(abs(r["G"][0][k][loc] - xs[loc]) / abs(xs[loc]) for k, xs in enumerate(exact))
+        tr = max(np.linalg.norm(b - (z * (Sc @ r["G"][0][k]) - Hc @ r["G"][0][k])) for k, z in enumerate(shifts))
+        print(f"[fullsize] cfg3 FP32 (M_j {st[4]}, {shifts.size} shifts, audit {audit}): max rel err G_jj {wg:.2e}, "
+              f"x {wx:.2e}; max true residual {tr:.2e}; outer {st[0]}, replacements {st[6]}, "
+              f"FP64 re-solve iterations {st[7]}", flush=True)
+        res[audit] = r
+    r = res[1]
+    assert np.all(r["status"] == CONVERGED), r["status"]
+    assert np.all(r["resid"] <= tol * 1.0001)
+    for k, (z, xs) in enumerate(zip(shifts, exact)):
+        err = np.linalg.norm(r["G"][0][k] - xs)
+        bound = 2.0 * tol / (abs(z.imag) * lam)
+        assert err <= bound, (k, err, bound)

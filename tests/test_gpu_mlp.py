@@ -89,12 +89,13 @@ def test_adam_steps_match_oracle(B):
 
 
 def test_learned_order_on_solver_logs(B):
-    """Train on iteration counts the solver logs, predict for fresh RHS, and
-    check that the learned queue order leaves every result unchanged; report
-    solve times of index order, by-size order, learned order and the order of
-    the true costs."""
+    """Train on iteration counts the solver logs (scocg_mlp_train), let
+    scocg_schedule order fresh RHS by their predicted cost, and check that
+    order against the host sort of predicted iterations x block entries, and
+    that every queue order leaves every result unchanged; report solve times
+    of index order, by-size order, learned order and the order of the true
+    costs."""
     import torch
-    from paper_1402_7285_amd import binning
     base = dict(lattice="fcc", L=5, bdim=9, hop=(0.0, 0.5), s_scale=0.03, K=16, eta=0.05, radius=(1.0, 2.2))
     train_p = make_problem(nrhs=192, seed_key=(21, 1, 1), **base)
     test_p = make_problem(nrhs=192, seed_key=(21, 2, 2), mats_key=(21, 1, 1), **base)
@@ -103,27 +104,37 @@ def test_learned_order_on_solver_logs(B):
     feats = plan.features().cpu().numpy()
     y = np.log(r["stats"][:, 0].astype(np.float64))
     rg = rngs_for((21, 1, 1))
-    model = binning.train(feats, y, mlp_init_weights(rg["mlp_init"]), rg["mlp_shuffle"], epochs=150, batch=32,
-                          lr=3e-3)
-    best_val = min(h[2] for h in model.history)
-    print(f"[mlp] train/val loss first {model.history[0][1:]} last {model.history[-1][1:]} best val {best_val:.3f}",
-          flush=True)
-    assert best_val < model.history[0][2]
+    w0 = mlp_init_weights(rg["mlp_init"])
+    model, best_val = B.scocg_mlp_train(feats, y, init_weights=w0, seed=21, epochs=150, batch=32, lr=3e-3)
+    # the untrained network (same z-scoring) against the trained one, over all training samples
+    untrained = model.copy()
+    untrained[: w0.size] = w0
+    mse0 = float(np.mean((B.scocg_mlp_predict(untrained, feats) - y) ** 2))
+    mse1 = float(np.mean((B.scocg_mlp_predict(model, feats) - y) ** 2))
+    print(f"[mlp] training MSE untrained {mse0:.3f} trained {mse1:.3f}, best validation {best_val:.3f}", flush=True)
+    assert mse1 < 0.5 * mse0 and best_val < mse0
     Pt, plan_t = _plan(B, test_p, tol=1e-8)
     ref = plan_t.solve()
     ft = plan_t.features().cpu().numpy()
-    pred = binning.predict(model, ft)
-    ent = binning.entries_per_rhs(ft)
+    pred = B.scocg_mlp_predict(model, ft).astype(np.float64)
+    ent = ft[:, 0].astype(np.float64) * ft[:, 1].astype(np.float64)
     truth = ref["stats"][:, 0].astype(np.float64)
     corr = np.corrcoef(pred, np.log(truth))[0, 1]
     print(f"[mlp] correlation of predicted and true log iterations on fresh RHS: {corr:.3f}", flush=True)
-    orders = {"index": np.arange(test_p.nrhs, dtype=np.int32),
-              "by_size": binning.order_longest_first(ent),
-              "learned": binning.order_longest_first(np.exp(pred) * ent),
-              "true_cost": binning.order_longest_first(truth * ent)}
+    # the library's schedule is the stable decreasing sort of exp(pred) x entries
+    order_l, cost_l = plan_t.schedule(model)
+    np.testing.assert_allclose(cost_l, np.exp(pred) * ent, rtol=1e-5)
+    assert np.all(np.diff(cost_l[order_l]) <= 0)
+    assert np.array_equal(np.sort(order_l), np.arange(test_p.nrhs))
+    order_s, cost_s = plan_t.schedule(None)
+    assert np.array_equal(cost_s, ent.astype(np.float32))
+    assert np.array_equal(order_s, np.argsort(-ent, kind="stable"))
+    orders = {"index": None, "by_size": order_s, "learned": order_l,
+              "true_cost": np.argsort(-(truth * ent), kind="stable").astype(np.int32)}
     times = {}
+    Po, po = _plan(B, test_p, tol=1e-8, slots=24)
     for name, order in orders.items():
-        Po, po = _plan(B, test_p, tol=1e-8, order=order, slots=24)
+        po.set_order(order)
         bufs = po.alloc_outputs()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
