@@ -513,6 +513,33 @@ scocg_status scocg_solve_device(scocg_problem* P, const scocg_options* opt, int3
                                 const scocg_rhs_spec* spec, scocg_z* out, int32_t* iters, int8_t* status,
                                 double* resid, void* stream);
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve of
+ * scocg_solve_device with no device allocation or release at all.  Every
+ * piece of per-call device memory (shifts, RHS records, requested rows, queue,
+ * counters and the workgroups' working memory) is carved from one fixed array
+ * of 64 MiB per device that the library holds from its load until the process
+ * ends.  The caller still passes the outputs (device buffers, as
+ * scocg_solve_device).  Runs the one-workgroup solver of the two real
+ * Lanczos-basis methods (opt->method COCG_LANCZOS or QMR, FP64, SELECTED_G
+ * output, every RHS on the whole system; E_UNSUPPORTED otherwise) with S as
+ * stored; as many workgroups run at once as the array holds (at most one per
+ * RHS, the device's compute units times occupancy, and opt->slots if set).
+ * E_ARG when one workgroup's working memory (roughly 64 M + 48 K n_out bytes
+ * for M rows, K shifts, n_out requested rows) does not fit the array.  The
+ * host arrays are copied before the call returns; the solve itself is then
+ * enqueued on `stream` asynchronously.  All calls on one device share its
+ * array, which keeps the last call's contents: calls that overlap on one
+ * device (two host threads, or two streams whose solves run at once) race and
+ * must be serialised by the caller.  No pending state is kept: synchronise
+ * `stream` and read the status buffer (no scocg_sync).
+ */
+scocg_status scocg_solve_device_noalloc(scocg_problem* P, const scocg_options* opt, int32_t nshift,
+                                        const scocg_z* shifts, int32_t nrhs, const int32_t* rhs_index,
+                                        const scocg_rhs_spec* spec, scocg_z* out, int32_t* iters,
+                                        int8_t* status, double* resid, void* stream);
+
+/*
  * Waits for every scocg_solve_device of P still pending (on its stream) and
  * frees their plans.  Returns OK, W_PARTIAL if some pair of those solves
  * did not converge (read from their status buffers; a solve given status =

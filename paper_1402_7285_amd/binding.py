@@ -35,7 +35,7 @@ EXPORTS = (
     "scocg_mlp_train_step", "scocg_plan_integrate", "scocg_matrix_from_mtx", "scocg_matrix_shape",
     "scocg_matrix_export_bsr", "scocg_solve_device", "scocg_sync", "scocg_mlp_cfg_default",
     "scocg_mlp_model_floats", "scocg_mlp_train", "scocg_mlp_predict", "scocg_plan_cohp", "scocg_autotune_team",
-    "scocg_plan_set_order", "scocg_schedule",
+    "scocg_solve_device_noalloc", "scocg_plan_set_order", "scocg_schedule",
 )
 
 
@@ -110,6 +110,8 @@ def _declare(lib):
                              C.POINTER(scocg_rhs_spec), _VP, _VP, _VP, _VP]),
         "scocg_solve_device": (st, [_VP, C.POINTER(scocg_options), i32, _VP, i32, _VP,
                                     C.POINTER(scocg_rhs_spec), _VP, _VP, _VP, _VP, _VP]),
+        "scocg_solve_device_noalloc": (st, [_VP, C.POINTER(scocg_options), i32, _VP, i32, _VP,
+                                            C.POINTER(scocg_rhs_spec), _VP, _VP, _VP, _VP, _VP]),
         "scocg_sync": (st, [_VP]),
         "scocg_mlp_cfg_default": (None, [C.POINTER(scocg_mlp_cfg)]),
         "scocg_mlp_model_floats": (i64, []),
@@ -353,6 +355,17 @@ def scocg_solve_device(problem, opt, shifts, rhs_index, spec: _Spec, out, iters=
     return _check(load().scocg_solve_device(problem, C.byref(opt), int(z.size), zp, int(rhs.size), _ptr(rhs),
                                             C.byref(spec.struct), _tptr(out), _tptr(iters), _tptr(status),
                                             _tptr(resid), _sp(stream)))
+
+
+def scocg_solve_device_noalloc(problem, opt, shifts, rhs_index, spec: _Spec, out, iters=None, status=None,
+                               resid=None, stream=None):
+    """The allocation-free device-buffer solve (one-workgroup Lanczos-basis
+    solver on the library's fixed per-device array); enqueued on ``stream``."""
+    z, zp = _shifts(shifts)
+    rhs = np.ascontiguousarray(rhs_index, dtype=np.int32)
+    return _check(load().scocg_solve_device_noalloc(problem, C.byref(opt), int(z.size), zp, int(rhs.size),
+                                                    _ptr(rhs), C.byref(spec.struct), _tptr(out), _tptr(iters),
+                                                    _tptr(status), _tptr(resid), _sp(stream)))
 
 
 def scocg_sync(problem):

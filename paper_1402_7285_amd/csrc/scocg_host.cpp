@@ -1317,6 +1317,163 @@ extern "C" scocg_status scocg_solve_device(scocg_problem* P, const scocg_options
     return SCOCG_OK;
 }
 
+// ---------------------------------------------------------------------------
+// allocation-free device-buffer solve: the one-workgroup Lanczos-basis solver
+// with every piece of per-call device memory taken from the library's fixed
+// per-device array
+// ---------------------------------------------------------------------------
+extern "C" scocg_status scocg_solve_device_noalloc(scocg_problem* P, const scocg_options* opt_in, int32_t nshift,
+                                                   const scocg_z* shifts, int32_t nrhs, const int32_t* rhs_index,
+                                                   const scocg_rhs_spec* spec, scocg_z* out, int32_t* iters,
+                                                   int8_t* status, double* resid, void* stream) {
+    if (!P) return fail(SCOCG_E_ARG, "problem is NULL");
+    scocg_options opt;
+    if (opt_in) opt = *opt_in; else scocg_options_default(&opt);
+    if (opt.method != SCOCG_METHOD_COCG_LANCZOS && opt.method != SCOCG_METHOD_QMR)
+        return fail(SCOCG_E_UNSUPPORTED, "the allocation-free solve runs the Lanczos-basis methods");
+    if (opt.precision != SCOCG_FP64) return fail(SCOCG_E_UNSUPPORTED, "the allocation-free solve runs in FP64");
+    if (spec && spec->cluster_ptr) return fail(SCOCG_E_UNSUPPORTED, "the allocation-free solve needs the whole system");
+    if (spec && spec->out_mode == SCOCG_OUT_FULL_X) return fail(SCOCG_E_UNSUPPORTED, "SELECTED_G output only");
+    if (!(opt.tol > 0.0) || !(opt.inner_tol > 0.0) || opt.maxiter < 0 || opt.inner_maxiter < 0)
+        return fail(SCOCG_E_ARG, "bad tolerance or iteration cap");
+    if (nshift < 1 || nshift > 512) return fail(nshift < 1 ? SCOCG_E_ARG : SCOCG_E_UNSUPPORTED, "nshift must be in [1, 512]");
+    if (!shifts) return fail(SCOCG_E_ARG, "shifts is NULL");
+    for (int k = 0; k < nshift; ++k)
+        if (!std::isfinite(shifts[k].re) || !std::isfinite(shifts[k].im)) return fail(SCOCG_E_ARG, "shift %d not finite", k);
+    if (nrhs < 0 || (nrhs > 0 && !rhs_index)) return fail(SCOCG_E_ARG, "bad RHS list");
+    if (nrhs == 0) return SCOCG_OK;
+    if (!out) return fail(SCOCG_E_ARG, "out is NULL");
+    if (!scocg::supported_bdim(P->bd)) return fail(SCOCG_E_UNSUPPORTED, "block size %d not compiled in", P->bd);
+    if (spec && spec->order) {
+        std::vector<char> seen(nrhs, 0);
+        for (int32_t r = 0; r < nrhs; ++r) {
+            const int32_t o = spec->order[r];
+            if (o < 0 || o >= nrhs || seen[o]) return fail(SCOCG_E_ARG, "order is not a permutation");
+            seen[o] = 1;
+        }
+    }
+    HIP_TRY(hipSetDevice(P->device));
+    void* base = nullptr;
+    HIP_TRY(scocg::noalloc_scratch(P->device, &base));
+    HostMaps hm;
+    scocg_status st;
+    try {
+        st = build_maps(P, nrhs, rhs_index, spec, hm);
+    } catch (const std::bad_alloc&) {
+        return fail(SCOCG_E_NOMEM, "host allocation");
+    }
+    if (st != SCOCG_OK) return st;
+
+    // launch shape: the one-workgroup Lanczos-basis kernel, CG direction in LDS when it fits, S as stored
+    const bool gal = opt.method == SCOCG_METHOD_COCG_LANCZOS;
+    const int64_t Mp = std::max<int64_t>(64, (hm.maxM + 63) / 64 * 64);
+    int64_t maxout = 1;
+    for (const auto& r : hm.rhs) maxout = std::max<int64_t>(maxout, r.nout);
+    const int64_t nIp = (maxout + 63) / 64 * 64;
+    int nt = 0;
+    bool dl = false;
+    for (int cand : {opt.threads ? opt.threads : 1024, 1024, 512, 256}) {
+        if (cand != 256 && cand != 512 && cand != 1024) return fail(SCOCG_E_ARG, "threads must be 0, 256, 512 or 1024");
+        const bool d = P->has_S && scocg::qmr_lds_bytes(nshift, cand, Mp, true) <= 160 * 1024;
+        if (scocg::qmr_lds_bytes(nshift, cand, Mp, d) > 160 * 1024) continue;
+        if (scocg::qmr_private_bytes(P->bd, !P->has_S, gal, d, false, cand) == 0) {
+            nt = cand;
+            dl = d;
+            break;
+        }
+    }
+    if (!nt) return fail(SCOCG_E_UNSUPPORTED, "no spill-free launch shape for this problem");
+    const int64_t slot_bytes = scocg::qmr_slot_bytes(nshift, Mp, nIp);
+
+    // the fixed array, carved: queue | shifts | RHS and system records | requested rows | row offsets |
+    // queue order | per-RHS counters | workgroup slots (each carve 256-byte aligned)
+    const size_t cap = scocg::NOALLOC_SCRATCH_BYTES;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = (off + bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    const size_t o_queue = take(sizeof(int32_t));
+    const size_t o_z = take(sizeof(double) * 2 * nshift);
+    const size_t o_rhs = take(sizeof(RhsInfo) * hm.rhs.size());
+    const size_t o_sys = take(sizeof(SysInfo) * hm.sys.size());
+    const size_t o_outl = take(sizeof(int32_t) * std::max<size_t>(1, hm.outl.size()));
+    const size_t o_outoff = take(sizeof(int64_t) * hm.outoff.size());
+    const size_t o_order = take(sizeof(int32_t) * nrhs);
+    const size_t o_stats = take(sizeof(int64_t) * scocg::NSTAT * nrhs);
+    const size_t o_ws = off;
+    if (o_ws + (size_t)slot_bytes > cap)
+        return fail(SCOCG_E_ARG, "the allocation-free solve needs %zu bytes of working memory for one workgroup; "
+                                 "its fixed per-device array holds %zu", o_ws + (size_t)slot_bytes, cap);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess || cus <= 0) cus = 256;
+    const size_t lds = scocg::qmr_lds_bytes(nshift, nt, Mp, dl);
+    int per_cu = std::min(2, std::max(1, 2048 / nt));
+    per_cu = std::min<int>(per_cu, (int)std::max<size_t>(1, (160 * 1024) / lds));
+    int64_t slots = std::min<int64_t>({(int64_t)nrhs, (int64_t)cus * per_cu, (int64_t)((cap - o_ws) / slot_bytes)});
+    if (opt.slots > 0) slots = std::min<int64_t>(slots, opt.slots);
+
+    char* b = (char*)base;
+    std::vector<double> zz(2 * (size_t)nshift);
+    for (int k = 0; k < nshift; ++k) {
+        zz[2 * k] = shifts[k].re;
+        zz[2 * k + 1] = shifts[k].im;
+    }
+    std::vector<int32_t> order(nrhs);
+    for (int32_t r = 0; r < nrhs; ++r) order[r] = (spec && spec->order) ? spec->order[r] : r;
+    hipStream_t hs = (hipStream_t)stream;
+    // the host arrays are copied before this call returns (the copies end before the solve is enqueued)
+    HIP_TRY(hipMemcpyAsync(b + o_z, zz.data(), sizeof(double) * zz.size(), hipMemcpyHostToDevice, hs));
+    HIP_TRY(hipMemcpyAsync(b + o_rhs, hm.rhs.data(), sizeof(RhsInfo) * hm.rhs.size(), hipMemcpyHostToDevice, hs));
+    HIP_TRY(hipMemcpyAsync(b + o_sys, hm.sys.data(), sizeof(SysInfo) * hm.sys.size(), hipMemcpyHostToDevice, hs));
+    if (!hm.outl.empty())
+        HIP_TRY(hipMemcpyAsync(b + o_outl, hm.outl.data(), sizeof(int32_t) * hm.outl.size(), hipMemcpyHostToDevice, hs));
+    HIP_TRY(hipMemcpyAsync(b + o_outoff, hm.outoff.data(), sizeof(int64_t) * hm.outoff.size(), hipMemcpyHostToDevice,
+                           hs));
+    HIP_TRY(hipMemcpyAsync(b + o_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice, hs));
+    HIP_TRY(hipStreamSynchronize(hs));
+
+    KParams k{};
+    k.Hv = P->dH;
+    k.Sv = P->dS;
+    k.Hv64 = P->dH;
+    k.Sv64 = P->dS;
+    k.rowptr_l = P->dRowptr;
+    k.ecol = P->dCol;
+    k.egid = P->dIota;
+    k.sys = (const SysInfo*)(b + o_sys);
+    k.rhs = (const RhsInfo*)(b + o_rhs);
+    k.out_local = (const int32_t*)(b + o_outl);
+    k.out_off = (const int64_t*)(b + o_outoff);
+    k.order = (const int32_t*)(b + o_order);
+    k.z = (const double*)(b + o_z);
+    k.nrhs = nrhs;
+    k.K = nshift;
+    k.maxiter = opt.maxiter;
+    k.tol = opt.tol;
+    k.inner_tol = opt.inner_tol;
+    k.inner_tol_lo = opt.inner_tol_lo;
+    k.inner_maxiter = opt.inner_maxiter;
+    k.s_unit_diag = P->s_unit_diag ? 1 : 0;
+    k.ent_direct = 1;
+    k.queue = (int32_t*)(b + o_queue);
+    k.ws = b + o_ws;
+    k.slot_bytes = slot_bytes;
+    k.Mp = Mp;
+    k.nIp = nIp;
+    k.out = (double*)out;
+    k.iters = iters;
+    k.status = status;
+    k.resid = resid;
+    k.stats = (int64_t*)(b + o_stats);
+    (void)hipGetLastError();
+    // the queue counter starts at zero (a fill kernel: the last call's value is still there)
+    HIP_TRY(scocg::launch_fill_i32(k.queue, 0, 1, hs));
+    HIP_TRY(scocg::launch_qmr(k, P->bd, !P->has_S, gal, dl, false, nt, (int)slots, hs));
+    return SCOCG_OK;
+}
+
 extern "C" scocg_status scocg_sync(scocg_problem* P) {
     if (!P) return fail(SCOCG_E_ARG, "problem is NULL");
     if (P->pending.empty()) return SCOCG_OK;

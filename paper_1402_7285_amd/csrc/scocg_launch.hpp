@@ -8,6 +8,11 @@
 
 namespace scocg {
 
+// The allocation-free entry point's fixed device working memory (per device).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+// Device address of that memory on `device` (fetched once per device, then cached).
+hipError_t noalloc_scratch(int device, void** ptr);
+
 bool supported_bdim(int bd);
 size_t solver_lds_bytes(int K, int nt);
 // Working memory of one resident workgroup (bytes) for K shifts and Mp rows.
