@@ -273,8 +273,11 @@ int64_t scocg_plan_out_count(const scocg_plan* plan);
  * diagonal blocks, S is applied as I plus a plan-held copy of its nonzero
  * off-diagonal blocks; bit 6: the team solver runs (then [0] is the number of
  * workgroups of all teams and [3] the bytes of one team's working memory);
- * bit 7: its block products run on FP64 matrix cores; bit 8: its inner CG
- * keeps its vectors in registers and LDS.  [8] workgroups per
+ * bit 7: its block products run on FP64 matrix cores; bit 8: the inner CG
+ * keeps its vectors in registers and LDS (team solver, or the one-workgroup
+ * solver on ELL blocks at 512 threads); bit 9: with bit 5 in the
+ * one-workgroup solver, the off-diagonal blocks are held in ELL form (every
+ * block row padded to the same length).  [8] workgroups per
  * team (1 for the other solvers), [9] panel width (right-hand sides per team).
  */
 #define SCOCG_NINFO 10

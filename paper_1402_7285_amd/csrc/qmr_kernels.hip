@@ -47,6 +47,7 @@ struct Sys {
     int64_t gbase;
     int nrows;
     int M;
+    int ew;                // > 0: ELL form, ew entries per block row (rowptr unused)
 };
 
 // LDS: per shift the two previous rotations (c real, s complex), the running
@@ -166,6 +167,64 @@ __device__ __forceinline__ double row_dot(const double* __restrict__ A, const Sy
     return acc;
 }
 
+// The same row product on the ELL form (every block row has sy.ew entries,
+// at a * ew + u): no row-pointer load, and a chunk of CH entries (column
+// indices and blocks together) goes out at once, so a row costs ceil(ew / CH)
+// memory latencies instead of one for its extent plus one per chunk.
+template <int BD, int NT>
+struct ChunkEll {
+    static constexpr int v = (BD <= 4 ? 8 : 4) / (NT >= 1024 ? 2 : 1);
+    static constexpr int value = v < 1 ? 1 : v;
+};
+
+template <int BD, int NT, int CH>
+__device__ __forceinline__ double row_dot_ell(const double* __restrict__ A, const Sys& sy, int a, int r,
+                                              const double* __restrict__ p) {
+    constexpr bool QUAD = BD == 4 && NT % 64 == 0;
+    const int ew = sy.ew;
+    const int64_t e0 = (int64_t)a * ew;
+    double acc = 0.0;
+    for (int u0 = 0; u0 < ew; u0 += CH) {
+        int32_t b[CH];
+        double av[CH][BD];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            if (u0 + u < ew) {      // the same in every lane
+                const int64_t e = e0 + u0 + u;
+                b[u] = sy.ecol[e];
+#pragma unroll
+                for (int c = 0; c < BD; ++c) av[u][c] = A[(e * BD + r) * BD + c];
+            } else {
+                b[u] = a;
+#pragma unroll
+                for (int c = 0; c < BD; ++c) av[u][c] = 0.0;
+            }
+        }
+        double own[QUAD ? CH : 1];
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+            if constexpr (QUAD) own[u] = p[(int64_t)b[u] * BD + r];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const double* pb = p + (int64_t)b[u] * BD;
+#pragma unroll
+            for (int c = 0; c < BD; ++c) {
+                double pv;
+                if constexpr (QUAD) {
+                    if (c == 0) pv = quad_bcast<0>(own[u]);
+                    else if (c == 1) pv = quad_bcast<1>(own[u]);
+                    else if (c == 2) pv = quad_bcast<2>(own[u]);
+                    else pv = quad_bcast<3>(own[u]);
+                } else {
+                    pv = pb[c];
+                }
+                acc += av[u][c] * pv;
+            }
+        }
+    }
+    return acc;
+}
+
 // y = A x over this thread's rows; returns the partial x^T y.  UNIT: A is
 // I plus the blocks of sy (S with exactly-identity diagonal blocks, its
 // off-diagonal blocks alone in sy), so the identity part is x_i itself.
@@ -183,10 +242,26 @@ __device__ __forceinline__ double spmv_rows(const double* __restrict__ A, const 
     return part;
 }
 
+// UNIT on the ELL form: y = x + (off-diagonal blocks) x, CH entries per chunk.
+template <int BD, int NT, int CH = ChunkEll<BD, NT>::value>
+__device__ __forceinline__ double spmv_rows_ell(const double* __restrict__ A, const Sys& sy,
+                                                const double* __restrict__ x, double* __restrict__ y) {
+    double part = 0.0;
+    for (int i = threadIdx.x; i < sy.M; i += NT) {
+        const int a = i / BD, r = i - a * BD;
+        const double xi = x[i];
+        const double v = row_dot_ell<BD, NT, CH>(A, sy, a, r, x) + xi;
+        y[i] = v;
+        part += xi * v;
+    }
+    return part;
+}
+
 template <int BD, int NT, bool UNIT = false>
 __device__ __forceinline__ double spmv(const double* __restrict__ A, const Sys& sy, const double* __restrict__ x,
                                        double* __restrict__ y) {
     if constexpr (UNIT) {
+        if (sy.ew > 0) return spmv_rows_ell<BD, NT>(A, sy, x, y);
         return spmv_rows<BD, NT, true, true>(A, sy, x, y);        // off-diagonal copy: entry e is block e
     } else {
         if (sy.egid == nullptr) return spmv_rows<BD, NT, true, false>(A, sy, x, y);
@@ -232,6 +307,90 @@ __device__ int inner_cg(const double* __restrict__ S, const Sys& sy, const doubl
     return it;
 }
 
+// The same CG with this thread's rows of the residual and of the solution in
+// registers (rows i = tid + m NT, m < R; the search direction d stays in LDS,
+// the product S d in the workgroup's slot): per step the vector passes read
+// and write only S d in memory.  The arithmetic, and its order, is that of
+// inner_cg, so the results are bitwise the same.  The S product takes its
+// row's entries in chunks of 4 here, which leaves the registers the two
+// arrays need.  The row index is passed through an empty asm statement where
+// a pass begins, so the compiler forms each row's address where it is used
+// instead of computing all R of them once and holding (or spilling) them
+// across the solve.
+template <int NT>
+struct RegRows {
+    static constexpr int value = 16384 / NT;     // rows per thread held in registers
+};
+
+template <int BD, int NT, int R>
+__device__ int inner_cg_reg(const double* __restrict__ S, const Sys& sy, const double* __restrict__ t,
+                            double* __restrict__ q, double* __restrict__ d, double* __restrict__ w, double tt,
+                            double tol, int maxit, double* red) {
+    const int M = sy.M;
+    double rr_[R], qq_[R];
+    int tb0 = threadIdx.x;
+    asm volatile("" : "+v"(tb0));
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const int i = tb0 + m * NT;
+        const double v = i < M ? t[i] : 0.0;
+        rr_[m] = v;
+        qq_[m] = 0.0;
+        if (i < M) d[i] = v;
+    }
+    int it = 0;
+    if (tt != 0.0) {
+        __syncthreads();
+        const double stop = tol * sqrt(tt);
+        double rr = tt;
+        while (it < maxit && !(sqrt(rr) <= stop)) {
+            double dw[1] = {spmv_rows_ell<BD, NT, 4>(S, sy, d, w)};
+            block_sum<NT, 1>(dw, red);
+            const double a = rr / dw[0];
+            double rn[1] = {0.0};
+            int tb = threadIdx.x;
+            asm volatile("" : "+v"(tb));
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const int i = tb + m * NT;
+                if (i < M) {
+                    qq_[m] += a * d[i];
+                    const double s = rr_[m] - a * w[i];
+                    rr_[m] = s;
+                    rn[0] += s * s;
+                }
+            }
+            block_sum<NT, 1>(rn, red);
+            const double bt = rn[0] / rr;
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const int i = tb + m * NT;
+                if (i < M) d[i] = rr_[m] + bt * d[i];
+            }
+            __syncthreads();
+            rr = rn[0];
+            ++it;
+        }
+    }
+    asm volatile("" : "+v"(tb0));
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const int i = tb0 + m * NT;
+        if (i < M) q[i] = qq_[m];
+    }
+    return it;
+}
+
+// UNIT 0: S as stored; 1: S = I + its off-diagonal blocks; 2: as 1, on the ELL
+// form, with the CG's residual and solution in registers.
+template <int BD, int NT, int UNIT>
+__device__ __forceinline__ int inner_solve(const double* __restrict__ S, const Sys& sy, const double* __restrict__ t,
+                                           double* __restrict__ q, double* __restrict__ res, double* __restrict__ d,
+                                           double* __restrict__ w, double tt, double tol, int maxit, double* red) {
+    if constexpr (UNIT == 2) return inner_cg_reg<BD, NT, RegRows<NT>::value>(S, sy, t, q, d, w, tt, tol, maxit, red);
+    else return inner_cg<BD, NT, UNIT != 0>(S, sy, t, q, res, d, w, tt, tol, maxit, red);
+}
+
 // Complex Givens rotation [[c, s], [-conj(s), c]] with c >= 0 real that maps
 // (a, b) to (r, 0).
 __device__ __forceinline__ void givens(zc a, zc b, double& c, zc& s, zc& r) {
@@ -263,7 +422,7 @@ __host__ __device__ inline int64_t slot_bytes(int K, int64_t Mp, int64_t nIp) {
 // UNIT: S has exactly-identity diagonal blocks and the plan holds a copy of
 // its off-diagonal blocks alone (global system): the inner CG applies
 // S = I + (those blocks) and never reads the identity blocks.
-template <int BD, int NT, bool SID, bool GAL, bool DL, bool UNIT>
+template <int BD, int NT, bool SID, bool GAL, bool DL, int UNIT>
 __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L, double* ldsd) {
     const int tid = threadIdx.x;
     const int K = P.K;
@@ -276,16 +435,18 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L, doub
     sy.gbase = si.ent_base;
     sy.nrows = si.nrows;
     sy.M = si.nrows * BD;
+    sy.ew = 0;
     const int M = sy.M;
     const int64_t Mp = P.Mp, nIp = P.nIp;
     const double* Hb = (const double*)P.Hv64;
-    const double* Sb = UNIT ? P.s_vals : (const double*)P.Sv64;
+    const double* Sb = UNIT ? (P.s_ell_w > 0 ? P.s_ell_val : P.s_vals) : (const double*)P.Sv64;
     Sys syS = sy;
     if constexpr (UNIT) {
         syS.rowptr = P.s_rowptr;
-        syS.ecol = P.s_ecol;
+        syS.ecol = P.s_ell_w > 0 ? P.s_ell_col : P.s_ecol;
         syS.egid = nullptr;
         syS.gbase = 0;
+        syS.ew = P.s_ell_w;
     }
     const int nI = ri.nout;
     const int32_t* rows = P.out_local + ri.out_base;
@@ -315,8 +476,8 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L, doub
     }
     __syncthreads();
     double* q0 = SID ? t : q;
-    if constexpr (!SID) inner_total += inner_cg<BD, NT, UNIT>(Sb, syS, t, q, res, d, wcg, 1.0, P.inner_tol, P.inner_maxiter,
-                                                        L.red);
+    if constexpr (!SID) inner_total += inner_solve<BD, NT, UNIT>(Sb, syS, t, q, res, d, wcg, 1.0, P.inner_tol,
+                                                                 P.inner_maxiter, L.red);
     __syncthreads();
     const double beta0 = sqrt(q0[ri.b_local]);
     for (int i = tid; i < M; i += NT) {
@@ -369,8 +530,8 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L, doub
         block_sum<NT, 1>(tt, L.red);
         // ---- q = S^{-1} t, beta_{n+1} = sqrt(q^T t)
         double* qq = SID ? t : q;
-        if constexpr (!SID) inner_total += inner_cg<BD, NT, UNIT>(Sb, syS, t, q, res, d, wcg, tt[0], P.inner_tol,
-                                                            P.inner_maxiter, L.red);
+        if constexpr (!SID) inner_total += inner_solve<BD, NT, UNIT>(Sb, syS, t, q, res, d, wcg, tt[0], P.inner_tol,
+                                                                     P.inner_maxiter, L.red);
         double qt[1] = {0.0};
         if constexpr (SID) {
             qt[0] = tt[0];
@@ -555,7 +716,7 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L, doub
     __syncthreads();
 }
 
-template <int BD, int NT, bool SID, bool GAL, bool DL, bool UNIT>
+template <int BD, int NT, bool SID, bool GAL, bool DL, int UNIT>
 __global__ __launch_bounds__(NT) void k_sqmr(KParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_job;
@@ -575,50 +736,70 @@ __global__ __launch_bounds__(NT) void k_sqmr(KParams P) {
     }
 }
 
+// The register-resident form (UNIT 2) is built for 4x4 blocks at 512 threads.
+template <int BD, int NT>
+constexpr bool reg_form() { return BD == 4 && NT == 512; }
+
 template <int BD, int NT, bool GAL>
-static void launch_dl(const KParams& P, bool unit, int slots, hipStream_t st) {
+static hipError_t launch_dl(const KParams& P, int unit, int slots, hipStream_t st) {
     const size_t lds = lds_dir_offset(P.K, NT) + sizeof(double) * (size_t)P.Mp;
-    if (unit) hipLaunchKernelGGL((k_sqmr<BD, NT, false, GAL, true, true>), dim3(slots), dim3(NT), lds, st, P);
-    else hipLaunchKernelGGL((k_sqmr<BD, NT, false, GAL, true, false>), dim3(slots), dim3(NT), lds, st, P);
+    if (unit == 2) {
+        if constexpr (reg_form<BD, NT>())
+            hipLaunchKernelGGL((k_sqmr<BD, NT, false, GAL, true, 2>), dim3(slots), dim3(NT), lds, st, P);
+        else
+            return hipErrorInvalidValue;
+    } else if (unit) {
+        hipLaunchKernelGGL((k_sqmr<BD, NT, false, GAL, true, 1>), dim3(slots), dim3(NT), lds, st, P);
+    } else {
+        hipLaunchKernelGGL((k_sqmr<BD, NT, false, GAL, true, 0>), dim3(slots), dim3(NT), lds, st, P);
+    }
+    return hipSuccess;
 }
 
 template <int BD, int NT>
-static hipError_t launch_nt(const KParams& P, bool sid, bool gal, bool dl, bool unit, int slots, hipStream_t st) {
+static hipError_t launch_nt(const KParams& P, bool sid, bool gal, bool dl, int unit, int slots, hipStream_t st) {
     const size_t lds = lds_bytes(P.K, NT);
+    hipError_t e = hipSuccess;
     if (gal) {
-        if (sid) hipLaunchKernelGGL((k_sqmr<BD, NT, true, true, false, false>), dim3(slots), dim3(NT), lds, st, P);
-        else if (dl) launch_dl<BD, NT, true>(P, unit, slots, st);
-        else hipLaunchKernelGGL((k_sqmr<BD, NT, false, true, false, false>), dim3(slots), dim3(NT), lds, st, P);
+        if (sid) hipLaunchKernelGGL((k_sqmr<BD, NT, true, true, false, 0>), dim3(slots), dim3(NT), lds, st, P);
+        else if (dl) e = launch_dl<BD, NT, true>(P, unit, slots, st);
+        else hipLaunchKernelGGL((k_sqmr<BD, NT, false, true, false, 0>), dim3(slots), dim3(NT), lds, st, P);
     } else {
-        if (sid) hipLaunchKernelGGL((k_sqmr<BD, NT, true, false, false, false>), dim3(slots), dim3(NT), lds, st, P);
-        else if (dl) launch_dl<BD, NT, false>(P, unit, slots, st);
-        else hipLaunchKernelGGL((k_sqmr<BD, NT, false, false, false, false>), dim3(slots), dim3(NT), lds, st, P);
+        if (sid) hipLaunchKernelGGL((k_sqmr<BD, NT, true, false, false, 0>), dim3(slots), dim3(NT), lds, st, P);
+        else if (dl) e = launch_dl<BD, NT, false>(P, unit, slots, st);
+        else hipLaunchKernelGGL((k_sqmr<BD, NT, false, false, false, 0>), dim3(slots), dim3(NT), lds, st, P);
     }
-    return hipGetLastError();
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 template <int BD>
-static hipError_t launch_bd(const KParams& P, bool sid, bool gal, bool dl, bool unit, int nt, int slots,
+static hipError_t launch_bd(const KParams& P, bool sid, bool gal, bool dl, int unit, int nt, int slots,
                             hipStream_t st) {
     if (nt == 256) return launch_nt<BD, 256>(P, sid, gal, dl, unit, slots, st);
     if (nt == 1024) return launch_nt<BD, 1024>(P, sid, gal, dl, unit, slots, st);
     return launch_nt<BD, 512>(P, sid, gal, dl, unit, slots, st);
 }
 
-template <int BD, int NT, bool SID, bool GAL, bool DL, bool UNIT>
+template <int BD, int NT, bool SID, bool GAL, bool DL, int UNIT>
 static size_t priv_one() {
     hipFuncAttributes fa{};
     if (hipFuncGetAttributes(&fa, (const void*)k_sqmr<BD, NT, SID, GAL, DL, UNIT>) != hipSuccess) return (size_t)-1;
     return fa.localSizeBytes;
 }
 template <int BD, int NT, bool GAL>
-static size_t priv_var(bool sid, bool dl, bool unit) {
-    if (sid) return priv_one<BD, NT, true, GAL, false, false>();
-    if (dl) return unit ? priv_one<BD, NT, false, GAL, true, true>() : priv_one<BD, NT, false, GAL, true, false>();
-    return priv_one<BD, NT, false, GAL, false, false>();
+static size_t priv_var(bool sid, bool dl, int unit) {
+    if (sid) return priv_one<BD, NT, true, GAL, false, 0>();
+    if (dl) {
+        if (unit == 2) {
+            if constexpr (reg_form<BD, NT>()) return priv_one<BD, NT, false, GAL, true, 2>();
+            else return (size_t)-1;
+        }
+        return unit ? priv_one<BD, NT, false, GAL, true, 1>() : priv_one<BD, NT, false, GAL, true, 0>();
+    }
+    return priv_one<BD, NT, false, GAL, false, 0>();
 }
 template <int BD>
-static size_t priv_bd(bool sid, bool gal, bool dl, bool unit, int nt) {
+static size_t priv_bd(bool sid, bool gal, bool dl, int unit, int nt) {
     if (nt == 256) return gal ? priv_var<BD, 256, true>(sid, dl, unit) : priv_var<BD, 256, false>(sid, dl, unit);
     if (nt == 1024) return gal ? priv_var<BD, 1024, true>(sid, dl, unit) : priv_var<BD, 1024, false>(sid, dl, unit);
     return gal ? priv_var<BD, 512, true>(sid, dl, unit) : priv_var<BD, 512, false>(sid, dl, unit);
@@ -626,7 +807,7 @@ static size_t priv_bd(bool sid, bool gal, bool dl, bool unit, int nt) {
 
 }  // namespace qmr
 
-size_t qmr_private_bytes(int bd, bool sid, bool gal, bool dl, bool unit, int nt) {
+size_t qmr_private_bytes(int bd, bool sid, bool gal, bool dl, int unit, int nt) {
     switch (bd) {
         case 1: return qmr::priv_bd<1>(sid, gal, dl, unit, nt);
         case 4: return qmr::priv_bd<4>(sid, gal, dl, unit, nt);
@@ -641,10 +822,14 @@ size_t qmr_lds_bytes(int K, int nt, int64_t Mp, bool dl) {
 
 int64_t qmr_slot_bytes(int K, int64_t Mp, int64_t nIp) { return qmr::slot_bytes(K, Mp, nIp); }
 
-hipError_t launch_qmr(const KParams& P, int bd, bool sid, bool gal, bool dl, bool unit, int nt, int slots,
+hipError_t launch_qmr(const KParams& P, int bd, bool sid, bool gal, bool dl, int unit, int nt, int slots,
                       hipStream_t st) {
     if (dl && sid) return hipErrorInvalidValue;      // no inner CG when S = I
-    if (unit && (!dl || !P.s_rowptr || !P.s_ecol || !P.s_vals)) return hipErrorInvalidValue;
+    if (unit && (!dl || (P.s_ell_w > 0 ? (!P.s_ell_col || !P.s_ell_val) : (!P.s_rowptr || !P.s_ecol || !P.s_vals))))
+        return hipErrorInvalidValue;
+    // the register-resident form needs the ELL blocks and at most its rows per thread
+    if (unit == 2 && (bd != 4 || nt != 512 || P.s_ell_w <= 0 || P.Mp > (int64_t)qmr::RegRows<512>::value * 512))
+        return hipErrorInvalidValue;
     switch (bd) {
         case 1: return qmr::launch_bd<1>(P, sid, gal, dl, unit, nt, slots, st);
         case 4: return qmr::launch_bd<4>(P, sid, gal, dl, unit, nt, slots, st);

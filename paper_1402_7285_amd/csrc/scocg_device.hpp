@@ -95,13 +95,43 @@ __device__ __forceinline__ V quad_bcast2(const V& v) {
 }
 
 // ---------------------------------------------------------------------------
-// workgroup reductions (deterministic)
+// wavefront reductions by DPP row operations (no LDS traffic); every lane of
+// the wavefront must be active
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffLL), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)((unsigned long long)b >> 32), CTRL, ROWS, 0xF,
+                                               false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double readlane64(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffLL), lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// Sum over the 16 lanes of each row (every lane gets its row's sum).
+__device__ __forceinline__ double row16_sum(double v) {
+    v += dpp64<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]: lane ^ 1
+    v += dpp64<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]: lane ^ 2
+    v += dpp64<0x124, 0xF>(v);   // row_ror 4: the neighbouring quad
+    v += dpp64<0x128, 0xF>(v);   // row_ror 8: the other two quads
     return v;
 }
+// Sum over the whole wavefront (returned in every lane, a uniform value).
+__device__ __forceinline__ double wave_total(double v) {
+    v = row16_sum(v);
+    v += dpp64<0x142, 0xA>(v);   // row_bcast 15: rows 1, 3 add the last lane of rows 0, 2
+    v += dpp64<0x143, 0xC>(v);   // row_bcast 31: rows 2, 3 add lane 31 (rows 0 + 1)
+    return readlane64(v, 63);
+}
+
+// ---------------------------------------------------------------------------
+// workgroup reductions (deterministic)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) { return wave_total(v); }
 
 // Sum N doubles over the workgroup; every thread gets the totals.
 // `red` is LDS scratch of at least (NT/64)*N doubles.

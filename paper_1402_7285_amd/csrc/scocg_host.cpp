@@ -147,6 +147,10 @@ struct scocg_plan {
     int64_t* dsrow = nullptr;      // S's off-diagonal blocks alone (unit)
     int32_t* dscol = nullptr;
     double* dsval = nullptr;
+    int32_t* dsell_col = nullptr;  // the same blocks in ELL form (one-workgroup solver), ell_w per row
+    double* dsell_val = nullptr;
+    int ell_w = 0;
+    bool reg = false;              // one-workgroup inner CG with its residual and solution in registers
     int32_t* dorder = nullptr;
     int32_t* dqueue = nullptr;
     char* dws = nullptr;
@@ -552,6 +556,8 @@ extern "C" void scocg_plan_free(scocg_plan* pl) {
     dev_free(pl->dsrow);
     dev_free(pl->dscol);
     dev_free(pl->dsval);
+    dev_free(pl->dsell_col);
+    dev_free(pl->dsell_val);
     dev_free(pl->dorder);
     dev_free(pl->dqueue);
     dev_free(pl->dws);
@@ -854,38 +860,6 @@ extern "C" scocg_status scocg_plan_create(scocg_problem* P, const scocg_options*
     const size_t lds = pl->qmr ? scocg::qmr_lds_bytes(nshift, pl->nt, pl->Mp, pl->dl)
                                : scocg::solver_lds_bytes(nshift, pl->nt);
     if (lds > 160 * 1024) return bail(fail(SCOCG_E_UNSUPPORTED, "too many shifts for LDS"));
-    // a workgroup size whose kernel instance would spill registers to private memory is not launched:
-    // the first of (requested, 512, 256, 1024) that keeps every value in registers runs instead
-    if (!pl->team) {
-        const int tries[4] = {pl->nt, 512, 256, 1024};
-        for (int nt : tries) {
-            const size_t dl_lds = pl->qmr ? scocg::qmr_lds_bytes(nshift, nt, pl->Mp, pl->dl) : 0;
-            if (pl->qmr && dl_lds > 160 * 1024) continue;
-            const size_t priv = pl->qmr ? scocg::qmr_private_bytes(P->bd, !P->has_S, pl->gal, pl->dl,
-                                                                    pl->unit && pl->dl, nt)
-                                        : scocg::solver_private_bytes(P->bd, pl->proj ? 3 : pl->prec, !P->has_S, nt);
-            if (priv == 0) {
-                pl->nt = nt;
-                break;
-            }
-        }
-    }
-    const size_t lds_nt = pl->qmr ? scocg::qmr_lds_bytes(nshift, pl->nt, pl->Mp, pl->dl)
-                                  : scocg::solver_lds_bytes(nshift, pl->nt);
-    int per_cu = std::max(1, 2048 / pl->nt);
-    per_cu = std::min<int>(per_cu, (int)std::max<size_t>(1, (160 * 1024) / lds_nt));
-    per_cu = std::min(per_cu, 2);
-    int slots = opt.slots ? opt.slots : cus * per_cu;
-    slots = std::max(1, std::min(slots, std::max(1, nrhs)));
-    size_t freeb = 0, totb = 0;
-    if (hipMemGetInfo(&freeb, &totb) == hipSuccess && freeb > 0) {
-        const int64_t cap = (int64_t)(0.8 * (double)freeb) / std::max<int64_t>(1, pl->slot_bytes);
-        if (cap < 1) return bail(fail(SCOCG_E_NOMEM, "one workgroup slot (%lld bytes) exceeds free memory",
-                                      (long long)pl->slot_bytes));
-        slots = (int)std::min<int64_t>(slots, cap);
-    }
-    pl->slots = slots;
-
     // S = I + its off-diagonal blocks (Lanczos-basis forms on a global system whose diagonal blocks of S
     // are exactly I): a copy of the nonzero off-diagonal blocks in their own CSR, so that the inner CG
     // never reads an identity block
@@ -911,6 +885,77 @@ extern "C" scocg_status scocg_plan_create(scocg_problem* P, const scocg_options*
         if (scol_h.empty()) srow_h.clear();
         else pl->unit = true;
     }
+    // The same blocks in ELL form (every block row padded to the longest with its own column and a zero
+    // block) for the one-workgroup solver, when the rows are near-uniform (at most a quarter padding):
+    // its row product then needs no row extent and issues a row's index and block loads together.
+    std::vector<int32_t> ecol_ell;
+    std::vector<double> eval_ell;
+    if (pl->unit) {
+        const size_t bb = (size_t)P->bd * P->bd;
+        int64_t wmax = 0;
+        for (int64_t a = 0; a < P->nb; ++a) wmax = std::max<int64_t>(wmax, srow_h[a + 1] - srow_h[a]);
+        const int64_t total = srow_h[(size_t)P->nb];
+        if (wmax > 0 && wmax <= 16 && 4 * total >= 3 * wmax * P->nb) {
+            pl->ell_w = (int)wmax;
+            ecol_ell.assign((size_t)(P->nb * wmax), 0);
+            eval_ell.assign((size_t)(P->nb * wmax) * bb, 0.0);
+            for (int64_t a = 0; a < P->nb; ++a) {
+                for (int64_t u = 0; u < wmax; ++u) {
+                    const int64_t e = srow_h[a] + u;
+                    const size_t o = (size_t)(a * wmax + u);
+                    if (e < srow_h[a + 1]) {
+                        ecol_ell[o] = scol_h[(size_t)e];
+                        std::copy(sval_h.begin() + (size_t)e * bb, sval_h.begin() + (size_t)(e + 1) * bb,
+                                  eval_ell.begin() + o * bb);
+                    } else {
+                        ecol_ell[o] = (int32_t)a;
+                    }
+                }
+            }
+        }
+    }
+
+    // a workgroup size whose kernel instance would spill registers to private memory is not launched:
+    // the first of (requested, 512, 256, 1024) that keeps every value in registers runs instead
+    // (the Lanczos-basis forms on the ELL blocks at 512 threads first try the instance that keeps the inner
+    // CG's residual and solution in registers, when a thread's rows fit it)
+    if (!pl->team) {
+        const int tries[4] = {pl->nt, 512, 256, 1024};
+        bool found = false;
+        for (int nt : tries) {
+            const size_t dl_lds = pl->qmr ? scocg::qmr_lds_bytes(nshift, nt, pl->Mp, pl->dl) : 0;
+            if (pl->qmr && dl_lds > 160 * 1024) continue;
+            const bool reg = pl->qmr && pl->unit && pl->dl && pl->ell_w > 0 && P->bd == 4 && nt == 512 &&
+                             pl->Mp <= 32 * 512;
+            for (int um : {reg ? 2 : -1, pl->unit && pl->dl ? 1 : 0}) {
+                if (um < 0) continue;
+                const size_t priv = pl->qmr ? scocg::qmr_private_bytes(P->bd, !P->has_S, pl->gal, pl->dl, um, nt)
+                                            : scocg::solver_private_bytes(P->bd, pl->proj ? 3 : pl->prec, !P->has_S, nt);
+                if (priv == 0) {
+                    pl->nt = nt;
+                    pl->reg = um == 2;
+                    found = true;
+                    break;
+                }
+            }
+            if (found) break;
+        }
+    }
+    const size_t lds_nt = pl->qmr ? scocg::qmr_lds_bytes(nshift, pl->nt, pl->Mp, pl->dl)
+                                  : scocg::solver_lds_bytes(nshift, pl->nt);
+    int per_cu = std::max(1, 2048 / pl->nt);
+    per_cu = std::min<int>(per_cu, (int)std::max<size_t>(1, (160 * 1024) / lds_nt));
+    per_cu = std::min(per_cu, 2);
+    int slots = opt.slots ? opt.slots : cus * per_cu;
+    slots = std::max(1, std::min(slots, std::max(1, nrhs)));
+    size_t freeb = 0, totb = 0;
+    if (hipMemGetInfo(&freeb, &totb) == hipSuccess && freeb > 0) {
+        const int64_t cap = (int64_t)(0.8 * (double)freeb) / std::max<int64_t>(1, pl->slot_bytes);
+        if (cap < 1) return bail(fail(SCOCG_E_NOMEM, "one workgroup slot (%lld bytes) exceeds free memory",
+                                      (long long)pl->slot_bytes));
+        slots = (int)std::min<int64_t>(slots, cap);
+    }
+    pl->slots = slots;
 
     // ---- team (panel) solver of the Lanczos-basis methods
     if (pl->qmr && opt.team_size >= 0 && nrhs > 0) {
@@ -1052,6 +1097,10 @@ extern "C" scocg_status scocg_plan_create(scocg_problem* P, const scocg_options*
         if ((st = dev_upload(&pl->dscol, scol_h.data(), scol_h.size()))) return bail(st);
         if ((st = dev_upload(&pl->dsval, sval_h.data(), sval_h.size()))) return bail(st);
     }
+    if (!ecol_ell.empty()) {
+        if ((st = dev_upload(&pl->dsell_col, ecol_ell.data(), ecol_ell.size()))) return bail(st);
+        if ((st = dev_upload(&pl->dsell_val, eval_ell.data(), eval_ell.size()))) return bail(st);
+    }
     if ((st = dev_upload(&pl->dorder, order.data(), order.size()))) return bail(st);
     if (hipMalloc((void**)&pl->dqueue, sizeof(int32_t)) != hipSuccess) return bail(fail(SCOCG_E_NOMEM, "queue"));
     if (pl->team) {
@@ -1086,7 +1135,9 @@ extern "C" scocg_status scocg_plan_info(const scocg_plan* pl, int64_t* info) {
     const bool unit = pl->team ? (pl->variant == 2 || pl->variant == 4) : (pl->unit && pl->dl);
     const bool mfma = pl->team && pl->P->bd == 4 && pl->W % 4 == 0;
     info[7] = (pl->global ? 1 : 0) | (pl->proj ? 2 : 0) | (pl->qmr ? 4 : 0) | (pl->gal ? 8 : 0) | (dl ? 16 : 0) |
-              (unit ? 32 : 0) | (pl->team ? 64 : 0) | (mfma ? 128 : 0) | (pl->team && pl->ri ? 256 : 0);
+              (unit ? 32 : 0) | (pl->team ? 64 : 0) | (mfma ? 128 : 0) |
+              ((pl->team && pl->ri) || (!pl->team && unit && pl->reg) ? 256 : 0) |
+              (unit && !pl->team && pl->ell_w ? 512 : 0);
     if (pl->team) info[5] = (int64_t)pl->team_lds;
     info[8] = pl->team ? pl->G : 1;
     info[9] = pl->team ? pl->W : 1;
@@ -1138,6 +1189,9 @@ static KParams make_kparams(const scocg_plan* pl, scocg_z* out, int32_t* iters, 
     k.s_rowptr = pl->unit ? pl->dsrow : nullptr;
     k.s_ecol = pl->unit ? pl->dscol : nullptr;
     k.s_vals = pl->unit ? pl->dsval : nullptr;
+    k.s_ell_col = pl->unit && pl->ell_w ? pl->dsell_col : nullptr;
+    k.s_ell_val = pl->unit && pl->ell_w ? pl->dsell_val : nullptr;
+    k.s_ell_w = pl->unit ? pl->ell_w : 0;
     k.queue = pl->dqueue;
     k.ws = pl->dws;
     k.slot_bytes = pl->slot_bytes;
@@ -1189,7 +1243,8 @@ extern "C" scocg_status scocg_plan_run(scocg_plan* pl, void* stream, scocg_z* ou
     }
     HIP_TRY(scocg::launch_fill_i32(pl->dqueue, 0, 1, st));
     if (pl->qmr)
-        HIP_TRY(scocg::launch_qmr(k, P->bd, !P->has_S, pl->gal, pl->dl, pl->unit && pl->dl, pl->nt, pl->slots, st));
+        HIP_TRY(scocg::launch_qmr(k, P->bd, !P->has_S, pl->gal, pl->dl, pl->unit && pl->dl ? (pl->reg ? 2 : 1) : 0,
+                                  pl->nt, pl->slots, st));
     else HIP_TRY(scocg::launch_solver(k, P->bd, pl->proj ? 3 : pl->prec, !P->has_S, pl->nt, pl->slots, st));
     return SCOCG_OK;
 }

@@ -25,12 +25,12 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 // Private (scratch) bytes per lane of the instance the one-workgroup launchers would run
 // ((size_t)-1 if it cannot be queried); instances with spills are not launched.
 size_t solver_private_bytes(int bd, int prec, bool sid, int nt);
-size_t qmr_private_bytes(int bd, bool sid, bool gal, bool dl, bool unit, int nt);
+size_t qmr_private_bytes(int bd, bool sid, bool gal, bool dl, int unit, int nt);
 // Shifted QMR over the real S-Lanczos basis (qmr_kernels.hip).
 size_t qmr_lds_bytes(int K, int nt, int64_t Mp, bool dl);
 int64_t qmr_slot_bytes(int K, int64_t Mp, int64_t nIp);
 // gal: the COCG (Galerkin) iterates on the same basis instead of the QMR ones.
-hipError_t launch_qmr(const KParams& P, int bd, bool sid, bool gal, bool dl, bool unit, int nt, int slots,
+hipError_t launch_qmr(const KParams& P, int bd, bool sid, bool gal, bool dl, int unit, int nt, int slots,
                       hipStream_t st);
 // Energy integration of a plan's output (integrate_kernels.hip).
 hipError_t launch_integrate(const double* G, const double* z, const double* w, const RhsInfo* rhs,

@@ -58,6 +58,12 @@ struct KParams {
     const int64_t* s_rowptr;
     const int32_t* s_ecol;
     const double* s_vals;
+    // the same blocks in ELL form, s_ell_w entries per block row (0: none):
+    // columns [nbrows][s_ell_w], blocks in that order; a row shorter than
+    // s_ell_w is padded with its own column and a zero block
+    const int32_t* s_ell_col;
+    const double* s_ell_val;
+    int32_t s_ell_w;
     // work queue and per-workgroup memory
     int32_t* queue;            // next RHS to hand out
     char* ws;

@@ -72,15 +72,21 @@ def _check(B, prob, ks, ref, r, tag):
           flush=True)
 
 
-def test_benchmark_instance_against_stored_oracle(setup):
+@pytest.mark.parametrize("threads", [1024, 512])
+def test_benchmark_instance_against_stored_oracle(setup, threads):
+    """Both instances the benchmark's autotuner chooses between: 1024 threads
+    (S's off-diagonal blocks in ELL form, the CG's vectors in memory) and 512
+    threads (the same blocks, the CG's residual and solution in registers)."""
     B, prob, ks, ref = setup
     P = B.Problem(prob.H, prob.S)
-    plan = B.Plan(P, prob.shifts[ks], prob.rhs, method=B.METHOD_COCG_LANCZOS, tol=1e-10, team_size=-1, threads=1024,
-                  out_ptr=prob.out_ptr, out_rows=prob.out_rows)
+    plan = B.Plan(P, prob.shifts[ks], prob.rhs, method=B.METHOD_COCG_LANCZOS, tol=1e-10, team_size=-1,
+                  threads=threads, out_ptr=prob.out_ptr, out_rows=prob.out_rows)
     info = plan.info
-    assert info["threads"] == 1024 and not info["global"] & 64, info        # one workgroup per RHS, 1024 threads
+    assert info["threads"] == threads and not info["global"] & 64, info     # one workgroup per RHS
     assert info["global"] & 16 and info["global"] & 32, info                 # direction in LDS, S = I + off-diagonal
-    _check(B, prob, ks, ref, plan.solve(), "one workgroup, 1024 threads")
+    assert info["global"] & 512, info                                        # ... in ELL form
+    assert bool(info["global"] & 256) == (threads == 512), info              # registers at 512 threads
+    _check(B, prob, ks, ref, plan.solve(), f"one workgroup, {threads} threads")
 
 
 def test_team_solver_against_stored_oracle(setup):
