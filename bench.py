@@ -475,7 +475,8 @@ def measured_traffic(args, form, alg_bytes):
     since, or this run is not the profiled one (its algorithmic bytes differ:
     another RHS count, iteration cap or tolerance)."""
     key = f"{args.workload}_{args.precision}_{form}"
-    path = os.path.join(ROOT, "profiles", f"k_scocg_{key}_traffic.json")
+    kernel = "k_sqmr" if form in ("qmr", "lanczos") else "k_scocg"
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{key}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
