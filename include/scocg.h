@@ -516,9 +516,10 @@ scocg_status scocg_solve_device(scocg_problem* P, const scocg_options* opt, int3
                                 const scocg_rhs_spec* spec, scocg_z* out, int32_t* iters, int8_t* status,
                                 double* resid, void* stream);
 /*
- * For callers that cannot allocate device memory (code under HIP graph
- * capture, tight serving loops, harnesses that forbid hipMalloc): the solve of
- * scocg_solve_device with no device allocation or release at all.  Every
+ * For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): the solve of scocg_solve_device with no
+ * device allocation or release at all.  (It waits on `stream` once, for the
+ * copies of its host arrays, so it is not a call to record into a graph.)  Every
  * piece of per-call device memory (shifts, RHS records, requested rows, queue,
  * counters and the workgroups' working memory) is carved from one fixed array
  * of 64 MiB per device that the library holds from its load until the process
