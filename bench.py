@@ -578,6 +578,7 @@ def main():
                    "team_size": plan.info["team_size"], "panel_width": plan.info["panel_width"],
                    "matrix_cores": bool(plan.info["global"] & 128),
                    "cg_vectors_in_registers": bool(plan.info["global"] & 256),
+                   "s_blocks_ell": bool(plan.info["global"] & 512),
                    "autotuned": r["autotuned"], "steps_requested": args.steps, "warmup_requested": args.warmup,
                    "time_budget_s": args.time_budget},
         **r["report"],
