@@ -141,6 +141,55 @@ def _cpu_worker(args):
     return (time.perf_counter() - t0) / max(1, res.n_outer)
 
 
+def _cpu_full_worker(args):
+    """One RHS of the workload solved to convergence by the oracle (the
+    Lanczos-basis form, requested rows, tol 1e-6); returns (rhs, seconds,
+    outer iterations, converged pairs)."""
+    prob, j, tol = args
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
+    from oracle import local_system, scocg_lanczos
+    from synth import bsr_to_scipy
+    H = bsr_to_scipy(prob.H)
+    S = bsr_to_scipy(prob.S) if prob.S is not None else None
+    Hc, Sc, loc, orb = local_system(prob, j, H, S)
+    b = np.zeros(orb.size)
+    b[loc] = 1.0
+    t0 = time.perf_counter()
+    res = scocg_lanczos(Hc, Sc, prob.shifts, b, tol, rows=np.searchsorted(orb, prob.outs(j)))
+    return j, time.perf_counter() - t0, int(res.n_outer), int(np.sum(res.status == 0))
+
+
+def cpu_full(prob, args):
+    """The CPU baseline without extrapolation: every RHS of the workload
+    solved to convergence by the oracle (the Lanczos-basis form the product
+    runs, requested rows), one RHS per process, args.cpu_full processes;
+    the rate is the converged pairs over the wall time of the whole run."""
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    done, good, outer = 0, 0, []
+    with ctx.Pool(args.cpu_full) as pool:
+        for j, sec, n_out, g in pool.imap_unordered(_cpu_full_worker, [(prob, j, args.tol) for j in range(prob.nrhs)]):
+            done += 1
+            good += g
+            outer.append(n_out)
+            print(f"[cpu-full] RHS {j}: {sec:.1f} s, {n_out} outer iterations, {g}/{prob.nshift} converged "
+                  f"({done}/{prob.nrhs} done, {time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    out = {"metric": METRIC, "value": good / wall, "unit": "solves/s", "kind": "oracle", "cores": args.cpu_full,
+           "workload": args.workload, "nrhs": prob.nrhs, "shifts": prob.nshift, "seconds": wall,
+           "converged_pairs": good, "pairs": prob.nrhs * prob.nshift,
+           "outer_iterations": {"mean": float(np.mean(outer)), "max": int(np.max(outer))},
+           "sample": f"every RHS ({prob.nrhs}) of the workload to convergence at tol {args.tol}, no extrapolation; "
+                     f"the oracle's Lanczos-basis form on requested rows, {args.cpu_full} processes with 1 BLAS "
+                     f"thread each"}
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration(nbytes):
     """A plain device copy of known size (for scaling FETCH_SIZE / WRITE_SIZE)."""
     import torch
@@ -517,6 +566,8 @@ def main():
                     help="cocg: shifted COCG with seed switching; qmr: shifted QMR over the real Lanczos basis; "
                          "cocg-lanczos: the COCG iterates on that basis")
     ap.add_argument("--copy-calib", type=int, default=0, help="only run a device copy of this many bytes")
+    ap.add_argument("--cpu-full", type=int, default=0,
+                    help="only run the CPU baseline on every RHS of the workload with this many processes")
     ap.add_argument("--no-autotune", action="store_true", help="use --threads/--slots as given")
     ap.add_argument("--team", type=int, default=0,
                     help="Lanczos-basis forms: workgroups per team (-1 one-workgroup solver, 0 autotuned)")
@@ -542,6 +593,11 @@ def main():
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the solver shards over RHS with no "
               f"communication during the solve, but multi-GPU runs are not implemented.", file=sys.stderr)
         sys.exit(2)
+
+    if args.cpu_full:
+        from synth import make_config
+        wl = WORKLOADS[args.workload]
+        return cpu_full(make_config(wl["cfg"], nrhs=args.nrhs or None, radius=wl.get("radius")), args)
 
     import torch
     from paper_1402_7285_amd import binding as B
