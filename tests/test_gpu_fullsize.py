@@ -116,22 +116,22 @@ def test_cfg2_full_size_smallest_clusters(B, form):
 def test_cfg2_full_size_largest_cluster_team(B):
     """Configuration 2's largest cluster among its first 64 RHS (r = 4a class,
     M_j = 9,495), solved by the team solver (the library's choice for
-    clusters this large: 8 workgroups split the cluster's rows), every 32nd
+    clusters this large: 16 workgroups split the cluster's rows), every 32nd
     shift and the last against sparse LU of the local system.  One workgroup
     alone needs over two minutes for this RHS; the team bounds the launch by
-    an eighth of that work plus its waits."""
+    a sixteenth of that work plus its waits."""
     full = make_config(2, nrhs=64)
     sizes = np.diff(full.cluster_ptr)
     prob = full.subset([int(np.argmax(sizes))])
     tol = 1e-6
     P, plan = _plan(B, prob, tol=tol, method=2)
-    assert plan.info["global"] & 64 and plan.info["team_size"] == 8, plan.info
+    assert plan.info["global"] & 64 and plan.info["team_size"] == 16, plan.info
     r = plan.solve()
     assert np.all(r["status"] == CONVERGED)
     assert np.all(r["resid"] <= tol)
     assert r["stats"][0][4] == 9 * int(sizes.max())
     every = list(range(0, prob.nshift, 32)) + [prob.nshift - 1]
-    _check_sampled(prob, r, every, tol, label="cfg2 largest cluster, team of 8")
+    _check_sampled(prob, r, every, tol, label="cfg2 largest cluster, team of 16")
     print(f"[fullsize] cfg2 largest cluster: {int(r['stats'][0][0])} outer iterations", flush=True)
 
 
