@@ -116,3 +116,52 @@ def test_qmr_argument_rules(B):
         P = B.Problem(prob.H, prob.S)
         B.Plan(P, prob.shifts, prob.rhs, method=7, out_ptr=prob.out_ptr, out_rows=prob.out_rows)
     assert ei.value.code == B.E_ARG
+
+
+def _ragged_S_problem():
+    """sc 5^3 with 4x4 blocks whose S lacks the bond blocks of every atom pair
+    with (a + b) % 10 == 0 (both orientations, so S stays symmetric; it stays
+    SPD, its off-diagonal part being small): block rows of S then hold 3 to 6
+    off-diagonal blocks, so the plan's ELL copy pads the shorter rows with
+    their own column and a zero block."""
+    prob = make_problem(name="sc5-ragged-S", lattice="sc", L=5, bdim=4, s_scale=0.03, K=12, eta=0.05, nrhs=4,
+                        seed_key=(5, 3, 5))
+    S = prob.S
+    lens = []
+    for a in range(S.nbrows):
+        n = 0
+        for e in range(S.rowptr[a], S.rowptr[a + 1]):
+            b = int(S.colidx[e])
+            if b != a and (a + b) % 10 == 0:
+                S.vals[e] = 0.0
+            elif b != a:
+                n += 1
+        lens.append(n)
+    return prob, np.array(lens)
+
+
+@pytest.mark.parametrize("threads", [512, 1024])
+def test_ell_padding_parity(B, threads):
+    """The one-workgroup Lanczos-basis kernel on S's off-diagonal blocks in
+    ELL form with padded rows (both instances the benchmark chooses between:
+    the register form at 512 threads, the memory form at 1024), against the
+    oracle of that form."""
+    prob, lens = _ragged_S_problem()
+    assert lens.min() < lens.max() and 4 * lens.sum() >= 3 * lens.max() * lens.size   # padded, under a quarter
+    P, plan = _plan(B, prob, method=B.METHOD_COCG_LANCZOS, threads=threads, team_size=-1)
+    info = plan.info
+    assert info["threads"] == threads and info["global"] & 32 and info["global"] & 512, info
+    assert bool(info["global"] & 256) == (threads == 512), info
+    r = plan.solve()
+    Hcsr, Scsr = bsr_to_scipy(prob.H), bsr_to_scipy(prob.S)
+    worst = 0.0
+    for j in range(prob.nrhs):
+        Hc, Sc, loc, orb = local_system(prob, j, Hcsr, Scsr)
+        b = np.zeros(orb.size)
+        b[loc] = 1.0
+        pos = np.searchsorted(orb, prob.outs(j))
+        res = scocg_lanczos(Hc, Sc, prob.shifts, b, prob.tol, rows=pos)
+        worst = max(worst, compare_rhs(r["G"][j], r["iters"][j], r["status"][j], res, Hc, Sc, prob.shifts,
+                                       b.astype(np.complex128), prob.tol, rows=pos, iter_frac=0.25, tag=f"rhs {j}"))
+    print(f"[ell] ragged S, threads={threads}: rows of {lens.min()}-{lens.max()} blocks, worst rel err {worst:.2e}",
+          flush=True)
