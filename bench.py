@@ -302,7 +302,8 @@ def measure_form(B, P, prob, kw, args, method, stream, warmup, steps, warm_budge
         if i + 1 >= n_steps:
             break
     wall = time.perf_counter() - t0
-    kernel_s = float(np.mean([a.elapsed_time(b) for a, b in ev])) / 1e3
+    step_ms = [a.elapsed_time(b) for a, b in ev]
+    kernel_s = float(np.mean(step_ms)) / 1e3
     status = bufs["status"].cpu().numpy()
     resid = bufs["resid"].cpu().numpy()
     good = int(np.sum((status == 0) & (resid <= 1e-6)))
@@ -325,6 +326,8 @@ def measure_form(B, P, prob, kw, args, method, stream, warmup, steps, warm_budge
         "outer_iterations": {"mean": float(stats[:, 0].mean()), "max": int(stats[:, 0].max())},
         "inner_per_outer": float(stats[:, 2].sum() / max(1, stats[:, 0].sum())),
         "fallback_iterations": int(stats[:, 7].sum()),
+        "step_ms": {"median": float(np.median(step_ms)), "min": float(np.min(step_ms)), "max": float(np.max(step_ms)),
+                    "all": [float(v) for v in step_ms]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args, form_key, alg),
                      "kernel": ("k_team (team solver)" if plan.info["global"] & 64 else
@@ -641,6 +644,22 @@ def main():
     }
     print(f"[bench] headline: {r['value']:.1f} solves/s over {r['steps']} timed steps "
           f"({r['ms_per_step'] / 1e3:.2f} s each)", file=sys.stderr, flush=True)
+    # the HBM bandwidth a plain device copy reaches on this GPU (1 GiB, best of three): the measured
+    # ceiling beside the published 8 TB/s
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b_ = torch.empty_like(a)
+    best = float("inf")
+    for _ in range(3):
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record()
+        b_.copy_(a)
+        c1.record()
+        torch.cuda.synchronize()
+        best = min(best, c0.elapsed_time(c1) / 1e3)
+    copy_gbs = 2 * a.numel() * 8 / best / 1e9
+    del a, b_
+    out["roofline"]["measured_copy_GBps"] = copy_gbs
+    out["roofline"]["frac_of_measured_copy"] = out["roofline"]["achieved"] / copy_gbs
     left = args.deadline - (time.perf_counter() - T_START)
     if args.method != "cocg" and not args.no_companion:
         # the seed-switching form of the same method, timed in the same run (one step, no warm-up beyond
