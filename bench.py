@@ -388,10 +388,12 @@ def chunked(B, P, prob, kw, args):
         pairs += st.size
         outer.append(stats[:, 0])
         launches.append({"rhs": sub.nrhs, "seconds": sec, "max_M": int(stats[:, 4].max()),
+                         "status_counts": np.bincount(st.ravel().astype(np.int64), minlength=5).tolist(),
                          "outer_max": int(stats[:, 0].max()), "team_size": plan.info["team_size"],
                          "threads": plan.info["threads"], "workgroups": plan.info["slots"],
                          "algorithmic_GBps": alg / sec / 1e9})
-        print(f"[bench] launch {len(launches)}: {sub.nrhs} RHS, {sec:.1f} s, converged {g}/{st.size}, "
+        print(f"[bench] launch {len(launches)}: {sub.nrhs} RHS, {sec:.1f} s, converged {g}/{st.size} "
+              f"(status counts {np.bincount(st.ravel().astype(np.int64), minlength=5).tolist()}), "
               f"largest cluster M={int(stats[:, 4].max())}, team {plan.info['team_size']}, "
               f"{alg / sec / 1e9:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
         del plan, bufs

@@ -621,6 +621,9 @@ __device__ bool solve_panel(const TParams& T, int panel, Team& tm, const Lds& L,
     for_elems<BD, NT, W>(a0, a1, [&](int row, int s, int c, int li) __attribute__((always_inline)) {
         st_pub(tprev + (int64_t)row * W + c, row == (int)COLV(L, C_BLOC, c) ? 1.0 : 0.0);
     });
+    // every member's rows of b are written before any product reads them (the first S product of
+    // q_0's CG reads the neighbours' rows; without this wait it can see the previous panel's vector)
+    if (!team_wait(tm, s_flag)) return false;
     double* qcur = SID ? tprev : qA;
     double* qnew = qB;
 
