@@ -1205,8 +1205,14 @@ __global__ __launch_bounds__(NT) void k_team(TParams T) {
     L.d = DL ? (double*)(smem + lds_fixed_bytes(NT, W, T.pairs_max)) : nullptr;
     const KParams& P = T.k;
     for (;;) {
+        // Between panels the rows change owners (each panel splits its own system's rows), and the
+        // ordinary stores of the last panel may still sit in another XCD's L2: every member writes its
+        // L2 back before it arrives and drops stale lines after the wait (agent-scope release and
+        // acquire, once per panel; the waits inside a panel order only the device-coherent accesses)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (tm.rank == 0 && threadIdx.x == 0) st_pub_i(tm.job, atomicAdd(P.queue, 1));
         if (!team_wait(tm, &s_flag)) break;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (threadIdx.x == 0) s_job = ld_pub_i(tm.job);
         __syncthreads();
         const int job = __builtin_amdgcn_readfirstlane(s_job);   // uniform: its loads are scalar

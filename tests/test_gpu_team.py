@@ -155,3 +155,32 @@ def test_team_argument_rules(B):
     # team_size -1: the one-workgroup solver
     P, plan = _plan(B, prob, B.METHOD_COCG_LANCZOS, team_size=-1)
     assert not plan.info["global"] & 64 and plan.info["team_size"] == 1
+
+
+@pytest.mark.parametrize("case", ["fcc3", "sc5"])
+def test_team_many_panels_per_team_repeatable(B, case):
+    """Two teams take sixteen order-N clusters of different sizes from the
+    work queue, so every team solves panel after panel on the same workspace
+    (each panel's first products read the neighbours' rows of b, which must
+    be this panel's, not the last one's).  Against the oracles, and three
+    runs bitwise the same: the team's sums are in a fixed order, so any
+    difference between runs is a read of another workgroup's data before it
+    was written."""
+    if case == "fcc3":
+        prob = make_problem(name="fcc3-clusters", lattice="fcc", L=3, bdim=9, hop=(0.0, 0.5), s_scale=0.03, K=12,
+                            eta=0.05, nrhs=16, radius=(1.0, 1.6), seed_key=(6, 6, 6))
+        G = 2
+    else:
+        prob = make_problem(name="sc5-clusters", lattice="sc", L=5, bdim=4, s_scale=0.03, K=8, eta=0.05, nrhs=16,
+                            radius=(1.0, 1.8), seed_key=(9, 2, 7))
+        G = 4
+    P, plan = _plan(B, prob, B.METHOD_COCG_LANCZOS, team_size=G, panel_width=1, threads=512, slots=2 * G)
+    assert plan.info["global"] & 64 and plan.info["team_size"] == G, plan.info
+    assert plan.info["slots"] == 2 * G, plan.info
+    r0 = _check(B, prob, plan, B.METHOD_COCG_LANCZOS, f"cocg-lanczos {case} 2 teams x 8 panels")
+    for rep in range(2):
+        r = plan.solve()
+        for j in range(prob.nrhs):
+            assert np.array_equal(r["G"][j], r0["G"][j]), (rep, j)
+        assert np.array_equal(r["status"], r0["status"]) and np.array_equal(r["iters"], r0["iters"]), rep
+        assert np.array_equal(r["stats"], r0["stats"]), rep
