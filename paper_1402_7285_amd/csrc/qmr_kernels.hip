@@ -344,7 +344,7 @@ __device__ int inner_cg_reg(const double* __restrict__ S, const Sys& sy, const d
         const double stop = tol * sqrt(tt);
         double rr = tt;
         while (it < maxit && !(sqrt(rr) <= stop)) {
-            double dw[1] = {spmv_rows_ell<BD, NT, 4>(S, sy, d, w)};
+            double dw[1] = {spmv_rows_ell<BD, NT, 6>(S, sy, d, w)};
             block_sum<NT, 1>(dw, red);
             const double a = rr / dw[0];
             double rn[1] = {0.0};
