@@ -119,10 +119,9 @@ struct Chunk {
     static constexpr int value = v < 1 ? 1 : v;
 };
 
-template <int BD, int NT, bool DIRECT>
+template <int BD, int NT, bool DIRECT, int CH = Chunk<BD, NT>::value>
 __device__ __forceinline__ double row_dot(const double* __restrict__ A, const Sys& sy, int a, int r,
                                           const double* __restrict__ p) {
-    constexpr int CH = Chunk<BD, NT>::value;
     constexpr bool QUAD = BD == 4 && NT % 64 == 0;
     const int64_t e0 = sy.rowptr[a], e1 = sy.rowptr[a + 1];
     double acc = 0.0;
@@ -228,14 +227,14 @@ __device__ __forceinline__ double row_dot_ell(const double* __restrict__ A, cons
 // y = A x over this thread's rows; returns the partial x^T y.  UNIT: A is
 // I plus the blocks of sy (S with exactly-identity diagonal blocks, its
 // off-diagonal blocks alone in sy), so the identity part is x_i itself.
-template <int BD, int NT, bool DIRECT, bool UNIT>
+template <int BD, int NT, bool DIRECT, bool UNIT, int CH = Chunk<BD, NT>::value>
 __device__ __forceinline__ double spmv_rows(const double* __restrict__ A, const Sys& sy,
                                             const double* __restrict__ x, double* __restrict__ y) {
     double part = 0.0;
     for (int i = threadIdx.x; i < sy.M; i += NT) {
         const int a = i / BD, r = i - a * BD;
         const double xi = x[i];
-        const double v = row_dot<BD, NT, DIRECT>(A, sy, a, r, x) + (UNIT ? xi : 0.0);
+        const double v = row_dot<BD, NT, DIRECT, CH>(A, sy, a, r, x) + (UNIT ? xi : 0.0);
         y[i] = v;
         part += xi * v;
     }
@@ -255,6 +254,17 @@ __device__ __forceinline__ double spmv_rows_ell(const double* __restrict__ A, co
         part += xi * v;
     }
     return part;
+}
+
+// The Lanczos step's product with H, outside the inner CG: with the CG's register arrays
+// dead there, 4x4 blocks at 512 threads take whole chunks of 8 entries (a row of an
+// order-one neighbour shell in one load latency after its extent).
+template <int BD, int NT>
+__device__ __forceinline__ double spmv_h(const double* __restrict__ A, const Sys& sy, const double* __restrict__ x,
+                                         double* __restrict__ y) {
+    constexpr int CH = BD == 4 && NT <= 512 ? 8 : Chunk<BD, NT>::value;
+    if (sy.egid == nullptr) return spmv_rows<BD, NT, true, false, CH>(A, sy, x, y);
+    return spmv_rows<BD, NT, false, false, CH>(A, sy, x, y);
 }
 
 template <int BD, int NT, bool UNIT = false>
@@ -312,17 +322,18 @@ __device__ int inner_cg(const double* __restrict__ S, const Sys& sy, const doubl
 // the product S d in the workgroup's slot): per step the vector passes read
 // and write only S d in memory.  The arithmetic, and its order, is that of
 // inner_cg, so the results are bitwise the same.  The S product takes its
-// row's entries in chunks of 4 here, which leaves the registers the two
-// arrays need.  The row index is passed through an empty asm statement where
-// a pass begins, so the compiler forms each row's address where it is used
-// instead of computing all R of them once and holding (or spilling) them
-// across the solve.
+// row's entries in chunks of 6 here (a row of six blocks in one load
+// latency), which still leaves the registers the two arrays need.  The row
+// index is passed through an empty asm statement where a pass (or a group
+// of rows) begins, so the compiler forms each row's address where it is
+// used instead of computing all R of them once and holding (or spilling)
+// them across the solve.
 template <int NT>
 struct RegRows {
     static constexpr int value = 16384 / NT;     // rows per thread held in registers
 };
 
-template <int BD, int NT, int R>
+template <int BD, int NT, int R, int RG = 8>
 __device__ int inner_cg_reg(const double* __restrict__ S, const Sys& sy, const double* __restrict__ t,
                             double* __restrict__ q, double* __restrict__ d, double* __restrict__ w, double tt,
                             double tol, int maxit, double* red) {
@@ -350,22 +361,61 @@ __device__ int inner_cg_reg(const double* __restrict__ S, const Sys& sy, const d
             double rn[1] = {0.0};
             int tb = threadIdx.x;
             asm volatile("" : "+v"(tb));
+            // Both passes take their rows in groups of RG: a group whose rows exist in every thread
+            // (m < M / NT) issues all its loads before any arithmetic, so a pass waits R / RG times
+            // for memory instead of R times; a group at the ragged end goes row by row.  The
+            // arithmetic is inner_cg's, fused the same way.
+            const int mfull = M / NT;
 #pragma unroll
-            for (int m = 0; m < R; ++m) {
-                const int i = tb + m * NT;
-                if (i < M) {
-                    qq_[m] += a * d[i];
-                    const double s = rr_[m] - a * w[i];
-                    rr_[m] = s;
-                    rn[0] += s * s;
+            for (int m0 = 0; m0 < R; m0 += RG) {
+                if (m0 + RG <= mfull) {
+                    int tg = tb + m0 * NT;
+                    asm volatile("" : "+v"(tg));
+                    double wv[RG], dv[RG];
+#pragma unroll
+                    for (int u = 0; u < RG; ++u) {
+                        wv[u] = w[tg + u * NT];
+                        dv[u] = d[tg + u * NT];
+                    }
+#pragma unroll
+                    for (int u = 0; u < RG; ++u) {
+                        qq_[m0 + u] = __builtin_fma(a, dv[u], qq_[m0 + u]);
+                        const double s = __builtin_fma(-a, wv[u], rr_[m0 + u]);
+                        rr_[m0 + u] = s;
+                        rn[0] = __builtin_fma(s, s, rn[0]);
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < RG; ++u) {
+                        const int i = tb + (m0 + u) * NT;
+                        if (i < M) {
+                            qq_[m0 + u] = __builtin_fma(a, d[i], qq_[m0 + u]);
+                            const double s = __builtin_fma(-a, w[i], rr_[m0 + u]);
+                            rr_[m0 + u] = s;
+                            rn[0] = __builtin_fma(s, s, rn[0]);
+                        }
+                    }
                 }
             }
             block_sum<NT, 1>(rn, red);
             const double bt = rn[0] / rr;
 #pragma unroll
-            for (int m = 0; m < R; ++m) {
-                const int i = tb + m * NT;
-                if (i < M) d[i] = rr_[m] + bt * d[i];
+            for (int m0 = 0; m0 < R; m0 += RG) {
+                if (m0 + RG <= mfull) {
+                    int tg = tb + m0 * NT;
+                    asm volatile("" : "+v"(tg));
+                    double dv[RG];
+#pragma unroll
+                    for (int u = 0; u < RG; ++u) dv[u] = d[tg + u * NT];
+#pragma unroll
+                    for (int u = 0; u < RG; ++u) d[tg + u * NT] = __builtin_fma(bt, dv[u], rr_[m0 + u]);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < RG; ++u) {
+                        const int i = tb + (m0 + u) * NT;
+                        if (i < M) d[i] = __builtin_fma(bt, d[i], rr_[m0 + u]);
+                    }
+                }
             }
             __syncthreads();
             rr = rn[0];
@@ -467,6 +517,7 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L, doub
     double* t = tA;        // u, then t
 
     const int maxiter = P.maxiter > 0 ? P.maxiter : max(1000, 4 * M);
+    constexpr int RG = 4;                  // rows per thread per group in the Lanczos step's vector passes
     int64_t inner_total = 0, sum_upd = 0;
 
     // ---- v_0 = S^{-1} b / beta_0, w_0 = b / beta_0  (b = e_j)
@@ -517,15 +568,30 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L, doub
     for (int n = 0; n < maxiter && L.ctl[1] < K && beta0 > 0.0 && isfinite(beta0); ++n) {
         n_outer = n + 1;
         // ---- u = H v, alpha = v^T u
-        double al[1] = {spmv<BD, NT>(Hb, sy, v, t)};
+        double al[1] = {spmv_h<BD, NT>(Hb, sy, v, t)};
         block_sum<NT, 1>(al, L.red);
         const double alpha = al[0];
         // ---- t = u - alpha w - beta w_prev, ||t||^2
         double tt[1] = {0.0};
-        for (int i = tid; i < M; i += NT) {
-            const double x_ = t[i] - alpha * w[i] - beta * wp[i];
-            t[i] = x_;
-            tt[0] += x_ * x_;
+        // (this pass and the two below take RG rows per thread at a time, every load of the
+        // group before its stores, rows past M clamped and masked; the sums in row order)
+        for (int i0 = tid; i0 < M; i0 += RG * NT) {
+            double tv[RG], wv[RG], pv[RG];
+#pragma unroll
+            for (int u = 0; u < RG; ++u) {
+                const int ic = i0 + u * NT < M ? i0 + u * NT : i0;
+                tv[u] = t[ic];
+                wv[u] = w[ic];
+                pv[u] = wp[ic];
+            }
+#pragma unroll
+            for (int u = 0; u < RG; ++u) {
+                if (i0 + u * NT < M) {
+                    const double x_ = tv[u] - alpha * wv[u] - beta * pv[u];
+                    t[i0 + u * NT] = x_;
+                    tt[0] += x_ * x_;
+                }
+            }
         }
         block_sum<NT, 1>(tt, L.red);
         // ---- q = S^{-1} t, beta_{n+1} = sqrt(q^T t)
@@ -536,7 +602,18 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L, doub
         if constexpr (SID) {
             qt[0] = tt[0];
         } else {
-            for (int i = tid; i < M; i += NT) qt[0] += q[i] * t[i];
+            for (int i0 = tid; i0 < M; i0 += RG * NT) {
+                double qv[RG], tv[RG];
+#pragma unroll
+                for (int u = 0; u < RG; ++u) {
+                    const int ic = i0 + u * NT < M ? i0 + u * NT : i0;
+                    qv[u] = q[ic];
+                    tv[u] = t[ic];
+                }
+#pragma unroll
+                for (int u = 0; u < RG; ++u)
+                    if (i0 + u * NT < M) qt[0] += qv[u] * tv[u];
+            }
             block_sum<NT, 1>(qt, L.red);
         }
         const bool bad = !isfinite(qt[0]) || !isfinite(alpha);
@@ -674,9 +751,21 @@ __device__ void solve_one(const KParams& P, int rj, char* ws, const Lds& L, doub
         // ---- next Lanczos vectors: v = q / beta_{n+1}, w_prev = w, w = t / beta_{n+1}
         if (beta_next > 0.0) {
             const double ib = 1.0 / beta_next;
-            for (int i = tid; i < M; i += NT) {
-                v[i] = qq[i] * ib;
-                t[i] *= ib;
+            for (int i0 = tid; i0 < M; i0 += RG * NT) {
+                double qv[RG], tv[RG];
+#pragma unroll
+                for (int u = 0; u < RG; ++u) {
+                    const int ic = i0 + u * NT < M ? i0 + u * NT : i0;
+                    qv[u] = qq[ic];
+                    tv[u] = t[ic];
+                }
+#pragma unroll
+                for (int u = 0; u < RG; ++u) {
+                    if (i0 + u * NT < M) {
+                        v[i0 + u * NT] = qv[u] * ib;
+                        t[i0 + u * NT] = tv[u] * ib;
+                    }
+                }
             }
         }
         __syncthreads();
