@@ -43,6 +43,7 @@
 // second reduction: two waits per CG step.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
 #include <utility>
 
 #include "scocg_device.hpp"
@@ -312,53 +313,83 @@ __device__ __forceinline__ void spmm(const double* __restrict__ A, const Sys& sy
         constexpr int CH = NT >= 1024 && CH0 > 1 ? CH0 / 2 : CH0;
         constexpr bool QUAD = BD == 4 && W == 1;
         const int i0 = a0 * BD, i1 = a1 * BD;
-        for (int i = i0 + tid; i < i1; i += NT) {
-            const int a = i / BD, r = i - a * BD;
-            const int64_t e0 = sy.rowptr[a], e1 = sy.rowptr[a + 1];
-            double acc[W];
+        // One loop per block-address form (entry number or map), chosen once per product, so that a
+        // chunk's index loads, and then all its block and vector loads, go out together: no branch
+        // between entries, and a padded slot re-reads the row's last entry and masks its value.
+        auto rows = [&](auto dir) __attribute__((always_inline)) {
+            constexpr bool DIRECT = decltype(dir)::value;
+            for (int i = i0 + tid; i < i1; i += NT) {
+                const int a = i / BD, r = i - a * BD;
+                const int64_t e0 = sy.rowptr[a], e1 = sy.rowptr[a + 1];
+                double acc[W];
 #pragma unroll
-            for (int c = 0; c < W; ++c) acc[c] = 0.0;
-            for (int64_t eb = e0; eb < e1; eb += CH) {
-                int32_t b[CH];
-                int64_t g[CH];
-                bool ok[CH];
+                for (int c = 0; c < W; ++c) acc[c] = 0.0;
+                // a chunk's column and block indices (padded slots: the row's last entry)
+                int32_t bn[CH], gn[CH];
+                auto load_idx = [&](int64_t eb) __attribute__((always_inline)) {
 #pragma unroll
-                for (int u = 0; u < CH; ++u) {
-                    ok[u] = eb + u < e1;
-                    const int64_t e = ok[u] ? eb + u : e1 - 1;
-                    b[u] = sy.ecol[e];
-                    g[u] = direct ? sy.gbase + e : (int64_t)sy.egid[e];
-                }
-                double av[CH][BD];
-                double own[QUAD ? CH : 1];
+                    for (int u = 0; u < CH; ++u) {
+                        const int64_t e = eb + u < e1 ? eb + u : e1 - 1;
+                        bn[u] = sy.ecol[e];
+                        gn[u] = DIRECT ? (int32_t)(eb + u) : sy.egid[e];
+                    }
+                };
+                if (e0 < e1) load_idx(e0);
+                for (int64_t eb = e0; eb < e1; eb += CH) {
+                    int32_t b[CH];
+                    int64_t g[CH];
+                    bool ok[CH];
 #pragma unroll
-                for (int u = 0; u < CH; ++u) {
-                    const int64_t off = (g[u] * BD + r) * BD;
+                    for (int u = 0; u < CH; ++u) {
+                        ok[u] = eb + u < e1;
+                        b[u] = bn[u];
+                        g[u] = DIRECT ? sy.gbase + (ok[u] ? eb + u : e1 - 1) : (int64_t)gn[u];
+                    }
+                    double av[CH][BD];
+                    double own[QUAD ? CH : 1];
+                    double xv[QUAD ? 1 : CH][QUAD ? 1 : BD * W];
 #pragma unroll
-                    for (int c = 0; c < BD; ++c) av[u][c] = ok[u] ? A[off + c] : 0.0;
-                    if constexpr (QUAD) own[u] = ld_pub(x + (int64_t)b[u] * 4 + r);
-                }
+                    for (int u = 0; u < CH; ++u) {
+                        const int64_t off = (g[u] * BD + r) * BD;
 #pragma unroll
-                for (int u = 0; u < CH; ++u) {
-                    if constexpr (QUAD) {
-                        acc[0] += av[u][0] * quad_bcast<0>(own[u]) + av[u][1] * quad_bcast<1>(own[u]) +
-                                  av[u][2] * quad_bcast<2>(own[u]) + av[u][3] * quad_bcast<3>(own[u]);
-                    } else {
-                        const double* xb = x + (int64_t)b[u] * BD * W;
+                        for (int c = 0; c < BD; ++c) {
+                            const double v = A[off + c];
+                            av[u][c] = ok[u] ? v : 0.0;
+                        }
+                        if constexpr (QUAD) {
+                            own[u] = ld_pub(x + (int64_t)b[u] * 4 + r);
+                        } else {
+                            const double* xb = x + (int64_t)b[u] * BD * W;
 #pragma unroll
-                        for (int c = 0; c < BD; ++c)
+                            for (int k = 0; k < BD * W; ++k) xv[u][k] = ld_pub(xb + k);
+                        }
+                    }
+                    // the next chunk's indices go out behind this chunk's loads (unconditionally: past
+                    // the row's end they re-read its last entry), so they arrive while it is summed
+                    load_idx(eb + CH);
 #pragma unroll
-                            for (int s = 0; s < W; ++s) acc[s] += av[u][c] * ld_pub(xb + c * W + s);
+                    for (int u = 0; u < CH; ++u) {
+                        if constexpr (QUAD) {
+                            acc[0] += av[u][0] * quad_bcast<0>(own[u]) + av[u][1] * quad_bcast<1>(own[u]) +
+                                      av[u][2] * quad_bcast<2>(own[u]) + av[u][3] * quad_bcast<3>(own[u]);
+                        } else {
+#pragma unroll
+                            for (int c = 0; c < BD; ++c)
+#pragma unroll
+                                for (int s = 0; s < W; ++s) acc[s] += av[u][c] * xv[u][c * W + s];
+                        }
                     }
                 }
-            }
 #pragma unroll
-            for (int s = 0; s < W; ++s) {
-                double y = acc[s];
-                if constexpr (UNIT) y += ld_pub(x + (int64_t)i * W + s);
-                ep(i, s, s, (i - i0) * W + s, y);
+                for (int s = 0; s < W; ++s) {
+                    double y = acc[s];
+                    if constexpr (UNIT) y += ld_pub(x + (int64_t)i * W + s);
+                    ep(i, s, s, (i - i0) * W + s, y);
+                }
             }
-        }
+        };
+        if (direct) rows(std::true_type{});
+        else rows(std::false_type{});
     }
 }
 
