@@ -341,13 +341,32 @@ __device__ int inner_cg_reg(const double* __restrict__ S, const Sys& sy, const d
     double rr_[R], qq_[R];
     int tb0 = threadIdx.x;
     asm volatile("" : "+v"(tb0));
+    const int mfull = M / NT;       // rows m < mfull exist in every thread
+    // r = d = t, q = 0: a whole group's loads of t go out before its stores (as in the passes below)
 #pragma unroll
-    for (int m = 0; m < R; ++m) {
-        const int i = tb0 + m * NT;
-        const double v = i < M ? t[i] : 0.0;
-        rr_[m] = v;
-        qq_[m] = 0.0;
-        if (i < M) d[i] = v;
+    for (int m0 = 0; m0 < R; m0 += RG) {
+        if (m0 + RG <= mfull) {
+            int tg = tb0 + m0 * NT;
+            asm volatile("" : "+v"(tg));
+            double tv[RG];
+#pragma unroll
+            for (int u = 0; u < RG; ++u) tv[u] = t[tg + u * NT];
+#pragma unroll
+            for (int u = 0; u < RG; ++u) {
+                rr_[m0 + u] = tv[u];
+                qq_[m0 + u] = 0.0;
+                d[tg + u * NT] = tv[u];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < RG; ++u) {
+                const int i = tb0 + (m0 + u) * NT;
+                const double v = i < M ? t[i] : 0.0;
+                rr_[m0 + u] = v;
+                qq_[m0 + u] = 0.0;
+                if (i < M) d[i] = v;
+            }
+        }
     }
     int it = 0;
     if (tt != 0.0) {
@@ -365,7 +384,6 @@ __device__ int inner_cg_reg(const double* __restrict__ S, const Sys& sy, const d
             // (m < M / NT) issues all its loads before any arithmetic, so a pass waits R / RG times
             // for memory instead of R times; a group at the ragged end goes row by row.  The
             // arithmetic is inner_cg's, fused the same way.
-            const int mfull = M / NT;
 #pragma unroll
             for (int m0 = 0; m0 < R; m0 += RG) {
                 if (m0 + RG <= mfull) {
