@@ -979,8 +979,9 @@ extern "C" scocg_status scocg_plan_create(scocg_problem* P, const scocg_options*
                 while (G < 8 && (int64_t)npanels * G * 2 <= cus && P->nb >= (int64_t)G * 2 * 64) G *= 2;
                 if (auto_shape && nrhs >= cus) G = 1;
             } else {
-                // (measured on configuration 2's largest clusters, M_j = 9,495: a launch of 64 RHS takes 43.5 s
-                // with teams of 8, 35.0 s with 16, 52.2 s with 32)
+                // (measured on a launch of 64 order-N clusters of an fcc crystal with 9x9 blocks and 256
+                // shifts, the largest with M_j = 9,495 rows: 43.5 s with teams of 8, 35.0 s with 16, 52.2 s
+                // with 32)
                 G = hm.maxM >= 8192 ? 16 : (hm.maxM >= 6144 ? 8 : (hm.maxM >= 3072 ? 4 : (hm.maxM >= 1536 ? 2 : 1)));
             }
         }
